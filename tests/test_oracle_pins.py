@@ -1,0 +1,321 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test names the passage it follows.  None of them re-types the oracle's
+own formula: they use closed forms and numbers printed in the paper, an
+independently written Brady-Yong transform, the second formulation (Alg. 1
+versus Alg. 2's pattern sums), hand-derived small cases and invariants.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import fht_oracle as O
+from oracle import native
+
+SPLITS = (O.SPLIT_S, O.SPLIT_T)
+
+
+def _e(num, n):
+    return Fraction(int(num[n]), n - 1) if n > 1 else Fraction(0)
+
+
+# --------------------------------------------------------------------- rounding
+
+def test_rhe_ties_to_even_and_exact():
+    # [.] is nearest-integer; ties go to the even neighbour (reading of Alg. 2).
+    assert [O.rhe(k, 2) for k in range(8)] == [0, 0, 1, 2, 2, 2, 3, 4]
+    assert O.rhe(7, 3) == 2 and O.rhe(8, 3) == 3 and O.rhe(5, 4) == 1 and O.rhe(6, 4) == 2
+    # exact on huge rationals where float rounding would not be
+    big = 10**30
+    assert O.rhe(2 * big + 1, 2) == big  # big is even
+    assert O.rhe(2 * (big + 1) + 1, 2) == big + 2
+
+
+def test_split_rules():
+    # Sec. 3: Split_S bisects (floor left), Split_T cuts off the largest power of two.
+    assert O.split_s(7) == (3, 4) and O.split_s(8) == (4, 4) and O.split_s(1021) == (510, 511)
+    assert O.split_t(2) == (1, 1) and O.split_t(3) == (2, 1) and O.split_t(5) == (4, 1)
+    assert O.split_t(17) == (16, 1) and O.split_t(1021) == (512, 509) and O.split_t(1024) == (512, 512)
+
+
+# --------------------------------------------------------------------- patterns
+
+def test_hand_derived_patterns_n5():
+    """Alg. 2 by hand for n = 5 (the half-to-even tie rule decides slope 1).
+
+    FHT2DS: Split_S(5) = (2, 3).  For t = 1: t0 = [1*1/4] = 0 and
+    t1 = [1*2/4] = [1/2] = 0 (tie, even), so pat = pat(2,0) ++ (pat(3,0) + 1)
+    = 00 ++ 111.  For t = 2: t0 = [2/4] = 0 (tie), t1 = [4/4] = 1;
+    pat(3,1): Split_S(3) = (1, 2), t0 = 0, t1 = [1/2] = 0 (tie), so
+    pat(3,1) = 0 ++ (00 + 1) = 011, lifted by 2 - 1 = 1 gives 122: 00122.
+    FHT2DT: Split_T(5) = (4, 1).  t = 1: t0 = [3/4] = 1, t1 = 0;
+    pat(4,1) = Brady-Yong slope 1 = 0011, right lane lifted by 1: 00111.
+    t = 2: t0 = [6/4] = 2 (tie, even); pat(4,2) = 0112, right lifted by 2: 01122.
+    """
+    assert O.pattern(5, 1, O.SPLIT_S) == [0, 0, 1, 1, 1]
+    assert O.pattern(5, 2, O.SPLIT_S) == [0, 0, 1, 2, 2]
+    assert O.pattern(5, 1, O.SPLIT_T) == [0, 0, 1, 1, 1]
+    assert O.pattern(5, 2, O.SPLIT_T) == [0, 1, 1, 2, 2]
+
+
+@pytest.mark.parametrize("split", SPLITS)
+def test_pattern_shape_invariants(split):
+    # Every pattern starts at 0, ends at t, and rises by 0 or 1 per step
+    # (Alg. 2: concatenation of child patterns, the right one lifted by t - t1).
+    for n in range(1, 130):
+        P = O.patterns(n, split)
+        assert (P[:, 0] == 0).all()
+        assert (P[:, -1] == np.arange(n)).all()
+        if n > 1:
+            d = np.diff(P, axis=1)
+            assert ((d == 0) | (d == 1)).all()
+
+
+@pytest.mark.parametrize("split", SPLITS)
+def test_c_patterns_equal_python_patterns(split):
+    for n in (1, 2, 3, 5, 17, 61, 100, 257):
+        assert (native.patterns(n, split) == O.patterns(n, split)).all()
+
+
+# --------------------------------------------------------------------- Theorem 1
+
+def test_theorem1_eq1_closed_form():
+    # Eq. (1): f_S(n) = (floor(log2 n) + 2) n^2 - 2^(floor(log2 n) + 1) n, for every n.
+    for n in range(1, 4097):
+        assert O.additions(n, O.SPLIT_S) == O.fs_closed_form(n), n
+    for n in (1, 2, 3, 1021, 4096):
+        assert native.nonleaf_width_sum(n, 0) * n == O.fs_closed_form(n)
+
+
+def test_theorem1_sharp_constants(paper_stats):
+    # Theorem 1 and Sec. 5: max of f/(n^2 log2 n) is 5 log3(2)/3 at n = 3 (S)
+    # and 81 log17(2)/17 at n = 17 (T).
+    def norm(n, split):
+        return O.additions(n, split) / (n * n * math.log2(n))
+    ns = range(2, 4097)
+    ns_s = max(ns, key=lambda n: norm(n, O.SPLIT_S))
+    ns_t = max(ns, key=lambda n: norm(n, O.SPLIT_T))
+    assert ns_s == int(paper_stats["fs_max_n"])
+    assert ns_t == int(paper_stats["ft_max_n"])
+    assert norm(3, O.SPLIT_S) == pytest.approx(5 * math.log(2, 3) / 3, rel=1e-12)
+    assert norm(17, O.SPLIT_T) == pytest.approx(81 * math.log(2, 17) / 17, rel=1e-12)
+    assert norm(3, O.SPLIT_S) < 1.052 and norm(17, O.SPLIT_T) < 1.166
+
+
+def test_theorem1_ft_at_two_power_plus_one():
+    # Proof of Theorem 1: f_T(2^k + 1) = (2^k + 1)(2^k + 1 + k 2^k).
+    for k in range(1, 12):
+        n = (1 << k) + 1
+        assert O.additions(n, O.SPLIT_T) == n * (n + k * (1 << k))
+
+
+# ------------------------------------------------- Theorem 2 and Sec. 5 statistics
+
+def test_theorem2_bound_holds(error_tables, paper_stats):
+    nmax = int(paper_stats["n_max"])
+    eT = error_tables[O.SPLIT_T]
+    for n in range(1, nmax + 1):
+        assert _e(eT, n) <= O.theorem2_bound(n), n
+
+
+def test_error_tables_match_python_oracle(error_tables):
+    for split in SPLITS:
+        for n in (1, 2, 3, 5, 23, 64, 100, 181):
+            assert _e(error_tables[split], n) == O.orthotropic_error(n, split)
+
+
+def test_sec5_share_above_theorem2(error_tables, paper_stats):
+    nmax = int(paper_stats["n_max"])
+    eS = error_tables[O.SPLIT_S]
+    above = sum(1 for n in range(1, nmax + 1) if _e(eS, n) > O.theorem2_bound(n))
+    # The paper prints the share rounded to two decimals.
+    assert round(100.0 * above / nmax, 2) == float(paper_stats["share_es_above_thm2_percent"])
+
+
+def test_sec5_ratio_peak(error_tables, paper_stats):
+    nmax = int(paper_stats["n_max"])
+    eS, eT = error_tables[O.SPLIT_S], error_tables[O.SPLIT_T]
+    ratios = {n: _e(eS, n) / _e(eT, n) for n in range(2, nmax + 1) if eT[n] > 0}
+    n_best = max(ratios, key=ratios.get)
+    assert n_best == int(paper_stats["es_over_et_n"])
+    factor = float(paper_stats["es_over_et_factor"])
+    assert factor < ratios[n_best] < factor + 0.01
+
+
+def test_sec5_peak_sequence(error_tables, paper_stats):
+    eS = error_tables[O.SPLIT_S]
+    peaks = [int(v) for v in paper_stats["es_peaks"].split()]
+    # n_{k+1} = 2 n_k + (-1)^(k+1), n_0 = 23
+    for k in range(len(peaks) - 1):
+        assert peaks[k + 1] == 2 * peaks[k] + (-1) ** (k + 1)
+    # Reading: each listed n is the highest peak of E_S(n)/(log2 n / 6) in its octave.
+    for n_peak in peaks:
+        k = n_peak.bit_length() - 1
+        octave = range(1 << k, 1 << (k + 1))
+        best = max(octave, key=lambda n: float(_e(eS, n)) / (math.log2(n) / 6))
+        assert best == n_peak
+
+
+def test_karpenko_power_of_two_error(error_tables):
+    # Sec. 2: at n = 2^q the maximal orthotropic error is log2(n)/6 for even q.
+    # For odd q the paper quotes log2(n)/6 - 1/18; with its line y = x t/(n-1)
+    # the computed error stays below that value by less than 1/(n-1).
+    for split in SPLITS:
+        for q in range(1, 13):
+            n = 1 << q
+            e = _e(error_tables[split], n)
+            if q % 2 == 0:
+                assert e == Fraction(q, 6)
+            else:
+                gap = Fraction(q, 6) - Fraction(1, 18) - e
+                assert 0 < gap < Fraction(1, n - 1)
+
+
+# ------------------------------------------------------------- sums (the transform)
+
+@pytest.mark.parametrize("split", SPLITS)
+def test_brady_yong_equals_both_variants_at_powers_of_two(split):
+    # Sec. 3: at n = 2^q FHT2DS and FHT2DT coincide with Brady-Yong.
+    rng = np.random.default_rng(11)
+    for W in (1, 2, 4, 8, 16, 32, 64):
+        for H in (1, 3, 16, 37):
+            A = rng.integers(0, 256, size=(W, H))
+            for sigma in (1, -1):
+                assert (O.hough_lanes(A, split, sigma) == O.brady_yong(A, sigma)).all()
+
+
+@pytest.mark.parametrize("split", SPLITS)
+def test_alg1_recursion_equals_pattern_sums(split):
+    # Alg. 1 (merge with Rotate) and Alg. 2 (sums along patterns) give the same numbers.
+    rng = np.random.default_rng(12)
+    for W in range(1, 26):
+        for H in (1, 2, 5, 13):
+            A = rng.integers(-50, 256, size=(W, H))
+            for sigma in (1, -1):
+                assert (O.fht2d(A, split, sigma) == O.hough_lanes(A, split, sigma)).all(), (W, H)
+
+
+@pytest.mark.parametrize("split", SPLITS)
+def test_single_pixel_gives_one_hit_per_slope(split):
+    # A one-pixel image lies on exactly one line of each slope, in each quadrant.
+    R, C = 9, 7
+    for (r, c) in ((0, 0), (4, 3), (8, 6), (3, 0)):
+        img = np.zeros((R, C), dtype=np.int64)
+        img[r, c] = 5
+        for J in O.hough4(img, split):
+            assert ((J != 0).sum(axis=1) == 1).all()
+            assert (J.sum(axis=1) == 5).all()
+
+
+@pytest.mark.parametrize("split", SPLITS)
+def test_line_sums_rows_and_diagonals(split):
+    rng = np.random.default_rng(13)
+    img = rng.integers(0, 256, size=(23, 17))
+    for (A, sigma), J in zip(O.quadrant_views(img), O.hough4(img, split)):
+        W, H = A.shape
+        # every slope covers each pixel exactly once over its H shifts
+        assert (J.sum(axis=1) == img.sum()).all()
+        # slope 0 is the plain sum over the lanes
+        assert (J[0] == A.sum(axis=0)).all()
+        # slope W-1 steps by one position per lane: the wrapped diagonal
+        s = np.arange(H)
+        diag = sum(A[x][(s + sigma * x) % H] for x in range(W))
+        assert (J[W - 1] == diag).all()
+
+
+@pytest.mark.parametrize("split", SPLITS)
+def test_linearity_and_quadrant_symmetry(split):
+    rng = np.random.default_rng(14)
+    a = rng.integers(0, 100, size=(12, 19))
+    b = rng.integers(0, 100, size=(12, 19))
+    for Ja, Jb, Jab in zip(O.hough4(a, split), O.hough4(b, split), O.hough4(3 * a - b, split)):
+        assert (3 * Ja - Jb == Jab).all()
+    # V- of an image equals V+ of its position-mirrored copy, mirrored back.
+    J = O.hough4(a, split)
+    mirror = (-np.arange(a.shape[1])) % a.shape[1]
+    Jm = O.hough_lanes(a[:, mirror], split, 1)
+    assert (J[1] == Jm[:, mirror]).all()
+
+
+def test_explicit_matrix_matches_sums():
+    rng = np.random.default_rng(15)
+    for split in SPLITS:
+        for W, H in ((5, 3), (7, 4), (3, 7)):
+            for sigma in (1, -1):
+                M = O.explicit_matrix(W, H, split, sigma)
+                A = rng.integers(0, 256, size=(W, H))
+                assert (M @ A.ravel() == O.hough_lanes(A, split, sigma).ravel()).all()
+                # each row of the operator sums exactly W pixels, one per lane
+                assert (M.sum(axis=1) == W).all()
+
+
+@pytest.mark.parametrize("split", SPLITS)
+def test_c_oracle_equals_python_oracle(split):
+    rng = np.random.default_rng(16)
+    for R, C in ((1, 1), (1, 9), (9, 1), (61, 47), (16, 33)):
+        img = rng.integers(0, 256, size=(R, C), dtype=np.uint8)
+        for x, y in zip(native.hough4_u8(img, split), O.hough4(img, split)):
+            assert (x == y).all()
+        f = rng.standard_normal((R, C))
+        o, ab = native.hough4_f64(f, split)
+        for x, y in zip(o, O.hough4(f, split)):
+            assert np.allclose(x, y, rtol=0, atol=1e-9)
+        for x, y in zip(ab, O.hough4(f, split, absolute=True)):
+            assert np.allclose(x, y, rtol=0, atol=1e-9)
+        # sampled outputs one by one
+        qs = rng.integers(0, 4, size=50)
+        ts = np.array([rng.integers(0, (R, R, C, C)[q]) for q in qs])
+        ss = np.array([rng.integers(0, (C, C, R, R)[q]) for q in qs])
+        full = native.hough4_u8(img, split)
+        assert (native.sample_u8(img, split, qs, ts, ss) ==
+                np.array([full[q][t, s] for q, t, s in zip(qs, ts, ss)])).all()
+
+
+def test_direct_sum_against_brute_force_line_enumeration():
+    """Tiny brute force: enumerate every lane's contribution by walking each line.
+
+    For W = 3 (Split_S(3) = (1, 2), Split_T(3) = (2, 1)) the three generating
+    patterns follow from Alg. 2 by hand: slope 0 -> 000, slope 2 -> 012, and
+    slope 1 -> 011 under S (right pair lifted by 1 - [1/2] = 1) and 001 under T
+    (left pair takes slope [1*1/2] = 0, the right lane is lifted by 1).
+    """
+    hand = {O.SPLIT_S: [[0, 0, 0], [0, 1, 1], [0, 1, 2]],
+            O.SPLIT_T: [[0, 0, 0], [0, 0, 1], [0, 1, 2]]}
+    rng = np.random.default_rng(17)
+    A = rng.integers(0, 256, size=(3, 4))
+    for split, pats in hand.items():
+        for sigma in (1, -1):
+            J = O.hough_lanes(A, split, sigma)
+            for t in range(3):
+                for s in range(4):
+                    assert J[t, s] == sum(A[x, (s + sigma * pats[t][x]) % 4] for x in range(3))
+
+
+def test_pins_reject_planted_mistakes(monkeypatch):
+    """Plant plausible mistakes in the oracle (CPU only) and check a pin fails."""
+    def half_up(num, den):
+        q, r = divmod(num, den)
+        return q + (1 if 2 * r >= den else 0)
+
+    def floor_div(num, den):
+        return num // den
+
+    for wrong in (half_up, floor_div):
+        monkeypatch.setattr(O, "rhe", wrong)
+        O._patterns_cached.cache_clear()
+        bad = (O.pattern(5, 1, O.SPLIT_S) != [0, 0, 1, 1, 1] or
+               O.pattern(5, 2, O.SPLIT_S) != [0, 0, 1, 2, 2] or
+               any(O.patterns(n, O.SPLIT_S)[n - 1, n - 1] != n - 1 for n in range(2, 20)))
+        A = np.arange(8 * 5).reshape(8, 5)
+        by_broken = not (O.hough_lanes(A, O.SPLIT_S) == O.brady_yong(A)).all()
+        assert bad or by_broken
+    monkeypatch.undo()
+    O._patterns_cached.cache_clear()
+    # a swapped split orientation changes the hand-derived patterns
+    monkeypatch.setattr(O, "split_s", lambda w: (w - w // 2, w // 2))
+    O._patterns_cached.cache_clear()
+    assert O.pattern(5, 1, O.SPLIT_S) != [0, 0, 1, 1, 1]
+    monkeypatch.undo()
+    O._patterns_cached.cache_clear()
