@@ -1,0 +1,182 @@
+/*
+ * fht.h - C ABI of the MI355X (gfx950) dyadic-pattern fast Hough transform.
+ *
+ * The transform is FHT2D of Kazimirov, Nikolaev, Rybakova and Terekhin,
+ * "Generalization of Brady-Yong Algorithm for Fast Hough Transform to Arbitrary
+ * Image Size" (arXiv 2411.07351), Sec. 3, Alg. 1: the image is split into two
+ * column ranges of widths Split(w) (Split_S = floor/ceil halves, the FHT2DS
+ * rule; Split_T = largest power of two on the left, the paper's FHT2DT rule),
+ * both halves are transformed recursively, and row t of the result is the sum
+ * of row [t k_0] of the left result and row [t k_1] of the right result
+ * circularly shifted by t - [t k_1], with k_P = (w_P - 1)/(w - 1) and [.] the
+ * nearest integer (ties to even, computed exactly).  Every output is therefore
+ * a sum along a dyadic pattern of Alg. 2, wrapped mod the image height.
+ *
+ * Quadrants.  For a row-major image of R rows and C columns four lane-major
+ * views A[x][y] are transformed:
+ *   q0 "V+": lanes x = image rows (W = R), positions y = columns (H = C), shift +1
+ *   q1 "V-": same lanes, shift -1 (negative slopes)
+ *   q2 "H+": lanes x = image columns (W = C), positions y = rows (H = R), shift +1
+ *   q3 "H-": same lanes, shift -1
+ * Output q is out_q[t][s] = sum_x A[x][(s + sign_q * pat_{W,t}(x)) mod H],
+ * t in [0, W), s in [0, H), row-major W x H.  The selected quadrants are
+ * stored back to back in q order in one output buffer.
+ *
+ * Types.  FHT_U8 images give int32 outputs (exact: 255 W < 2^31); FHT_F32
+ * gives float32; FHT_F64 gives float64.
+ *
+ * Memory and ownership.  All image, output and workspace pointers are device
+ * pointers (HIP) that the caller allocates and owns.  A plan owns its host
+ * tables and the device copies of them; it is immutable after creation and may
+ * be shared by threads and streams.  Calls that use the same workspace must not
+ * overlap.  The library allocates device memory only for plan tables
+ * (fht_plan_upload, or the first fht_forward of a plan on a device) and for
+ * batch tables (fht_batch_create).
+ *
+ * Errors.  No call aborts or throws.  Arguments are checked before anything
+ * is enqueued; launches are asynchronous on the given stream, so a device fault
+ * surfaces at the caller's next synchronisation.
+ */
+#ifndef FHT_H_
+#define FHT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FHT_OK = 0,
+    FHT_EINVAL = -1,  /* bad size, null pointer, bad quadrant mask or schedule */
+    FHT_EDTYPE = -2,  /* unknown dtype or mixed dtypes in one batch */
+    FHT_ENOMEM = -3,  /* host or device allocation failed */
+    FHT_EHIP = -4,    /* a HIP runtime call or kernel launch failed */
+    FHT_EBUSY = -5,   /* request does not fit the stated budget (serving admission) */
+    FHT_ENODEV = -6   /* no HIP device is available */
+} fht_status;
+
+typedef enum { FHT_U8 = 0, FHT_F32 = 1, FHT_F64 = 2 } fht_dtype;
+
+/* Sec. 3: FHT2DS (Split_S, floor/ceil halves) and FHT2DT (Split_T). */
+typedef enum { FHT_SPLIT_S = 0, FHT_SPLIT_T = 1 } fht_split;
+
+typedef struct fht_plan_s *fht_plan;
+typedef struct fht_batch_s *fht_batch;
+
+/*
+ * Tiling of the fused passes (not in the paper: the paper's recursion runs one
+ * level at a time).  Zero in a field means "library default".
+ *   s_tile      positions per work item (multiple of 16, <= 1024)
+ *   first_levels  tree levels fused in the first pass (1..8)
+ *   max_levels  tree levels fused in each later pass (1..10)
+ *   lds_budget  LDS bytes a work item may use (<= 65536)
+ *   t_tile      slope rows per work item in later passes (0 = choose)
+ */
+typedef struct {
+    int32_t s_tile;
+    int32_t first_levels;
+    int32_t max_levels;
+    int32_t lds_budget;
+    int32_t t_tile;
+} fht_schedule;
+
+/* Human-readable name of a status code (static storage). */
+const char *fht_status_string(fht_status s);
+
+/*
+ * Build a plan for rows x cols images of the given dtype and split rule
+ * (Sec. 3, Alg. 1).  quadrant_mask bit q selects output q (1..15).  sched may
+ * be NULL.  Host-only: needs no GPU.  On success *out owns the plan.
+ * Errors: FHT_EINVAL (rows or cols < 1 or > 65536, mask 0 or > 15, bad
+ * schedule), FHT_EDTYPE, FHT_ENOMEM.
+ */
+fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, fht_dtype dtype,
+                           fht_split split, uint32_t quadrant_mask, const fht_schedule *sched);
+
+/* Frees host and device tables of a plan; NULL is ignored.  The caller
+ * must make sure no enqueued work still uses the plan. */
+void fht_plan_destroy(fht_plan plan);
+
+/* Elements of the output buffer: sum over selected q of W_q * H_q. */
+size_t fht_plan_out_elems(fht_plan plan);
+
+/* Element offset of quadrant q in the output buffer, or -1 if not selected. */
+int64_t fht_plan_out_offset(fht_plan plan, int32_t q);
+
+/* Bytes of device workspace fht_forward needs (0 if none). */
+size_t fht_plan_workspace_bytes(fht_plan plan);
+
+/* Number of kernel launches one fht_forward enqueues. */
+int32_t fht_plan_num_launches(fht_plan plan);
+
+/* Copy the plan's tables to the current HIP device (idempotent).  Needed only
+ * before capturing fht_forward into a HIP graph.  Errors: FHT_ENODEV, FHT_ENOMEM,
+ * FHT_EHIP. */
+fht_status fht_plan_upload(fht_plan plan);
+
+/*
+ * Forward transform of one image (Alg. 1 for every selected quadrant).
+ *   d_img  device, row-major rows x cols of the plan's dtype (uint8/float/double)
+ *   d_out  device, fht_plan_out_elems elements (int32 for FHT_U8, else the dtype)
+ *   d_ws   device, fht_plan_workspace_bytes bytes (may be NULL when that is 0)
+ *   stream HIP stream (hipStream_t) or NULL for the null stream
+ * Asynchronous.  Errors: FHT_EINVAL (null pointers), FHT_ENODEV, FHT_EHIP.
+ */
+fht_status fht_forward(fht_plan plan, const void *d_img, void *d_out, void *d_ws, void *stream);
+
+/* Enqueues only launch `launch` (0 <= launch < fht_plan_num_launches) of
+ * fht_forward, with the same arguments.  Running launches 0, 1, ... in order
+ * on one stream equals fht_forward; it lets a caller time or interleave the
+ * fused passes.  Errors: as fht_forward, FHT_EINVAL for a bad index. */
+fht_status fht_forward_launch(fht_plan plan, int32_t launch, const void *d_img, void *d_out,
+                              void *d_ws, void *stream);
+
+/*
+ * Batched forward over n images of possibly different sizes (one plan each,
+ * all of one dtype and split): one launch per fused pass for the whole batch
+ * instead of per image.  fht_batch_create binds the device pointers and builds
+ * the batch's device work list; fht_batch_run enqueues it (it may be captured
+ * into a HIP graph).  d_ws must hold fht_batch_workspace_bytes bytes.
+ *   plans  host array of n plans (each must outlive the batch)
+ *   d_imgs host array of n device image pointers
+ *   d_outs host array of n device output pointers (fht_plan_out_elems each)
+ * Errors: FHT_EINVAL, FHT_EDTYPE (dtypes or splits differ), FHT_ENOMEM, FHT_EHIP.
+ */
+fht_status fht_batch_create(fht_batch *out, const fht_plan *plans, int32_t n,
+                            const void *const *d_imgs, void *const *d_outs);
+size_t fht_batch_workspace_bytes(fht_batch batch);
+int32_t fht_batch_num_launches(fht_batch batch);
+fht_status fht_batch_run(fht_batch batch, void *d_ws, void *stream);
+/* One launch of fht_batch_run (0 <= launch < fht_batch_num_launches). */
+fht_status fht_batch_run_launch(fht_batch batch, int32_t launch, void *d_ws, void *stream);
+void fht_batch_destroy(fht_batch batch);
+
+/*
+ * Host view of a plan's tables, for inspection and tests of the planner.
+ * Quadrant view v = 0 (lanes are image rows) or 1 (lanes are image columns).
+ * fht_plan_num_passes returns the number of fused passes of view v (or -1).
+ * fht_plan_pass_tables returns pointers into the plan (valid while it lives):
+ *   hdrs  n_progs x FHT_HDR_INTS ints: [0] first op, [1] loads, [2] stores,
+ *         [3] steps, [4] LDS elements, [5] all ops, [6] lanes-in level,
+ *         [7] lanes-out level, [8 + k] ops of step k
+ *   ops   4 ints each: load {lds, src row, position offset, count},
+ *         merge {lds dst, lds src0, lds src1, count} (dst = src0 + src1),
+ *         store {lds src, dst row, 0, count}
+ *   items 4 ints each: {program, 0, first position, 0}
+ *   s_tile positions per item.
+ */
+#define FHT_HDR_INTS 32
+int32_t fht_plan_num_passes(fht_plan plan, int32_t v);
+fht_status fht_plan_pass_tables(fht_plan plan, int32_t v, int32_t pass,
+                                const int32_t **hdrs, int32_t *n_progs,
+                                const int32_t **ops, int32_t *n_ops,
+                                const int32_t **items, int32_t *n_items,
+                                int32_t *s_tile);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FHT_H_ */

@@ -20,6 +20,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <omp.h>
+
 #define ORC_SPLIT_S 0
 #define ORC_SPLIT_T 1
 
@@ -278,4 +280,16 @@ int orc_error_numerators(int nmax, int split, int64_t *num)
         for (int i = 0; i < nmemo; ++i) free(memo[i].tab);
     }
     return rc;
+}
+
+/* Threads an OpenMP parallel region of this library uses. */
+int orc_num_threads(void)
+{
+    int n = 1;
+    #pragma omp parallel
+    {
+        #pragma omp single
+        n = omp_get_num_threads();
+    }
+    return n;
 }

@@ -43,6 +43,7 @@ def _load():
         lib.orc_hough_sample_u8.argtypes = [p, i32, i32, i32, i64, p, p, p, p]
         lib.orc_hough_sample_f64.argtypes = [p, i32, i32, i32, i64, p, p, p, p, p]
         lib.orc_error_numerators.argtypes = [i32, i32, p]
+        lib.orc_num_threads.argtypes = []
         _lib = lib
     return _lib
 
@@ -124,3 +125,8 @@ def error_numerators(nmax: int, split: int) -> np.ndarray:
     if _load().orc_error_numerators(nmax, split, _ptr(num)) != 0:
         raise ValueError("orc_error_numerators failed")
     return num
+
+
+def num_threads() -> int:
+    """OpenMP threads the C oracle runs on."""
+    return int(_load().orc_num_threads())

@@ -1,0 +1,348 @@
+"""ctypes binding of ``libfht.so`` (declared in ``include/fht.h``).
+
+The functions keep the C names and only marshal arguments: every step of the
+transform runs in the HIP kernels of the library.  ``Plan`` and ``Batch`` wrap
+them for torch tensors (torch supplies device memory and the stream).  If the
+library has not been built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfht.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2411_07351_amd.build`")
+
+# torch first: the library must bind to the HIP runtime torch already loaded,
+# because streams and device pointers are torch's.
+import torch  # noqa: E402,F401
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+__all__ = [
+    "FHT_U8", "FHT_F32", "FHT_F64", "FHT_SPLIT_S", "FHT_SPLIT_T", "FHT_HDR_INTS", "QUADRANTS",
+    "LIB_PATH", "EXPORTED", "FhtError", "fht_schedule", "Plan", "Batch", "hough",
+    "fht_status_string", "fht_plan_create", "fht_plan_destroy", "fht_plan_out_elems",
+    "fht_plan_out_offset", "fht_plan_workspace_bytes", "fht_plan_num_launches",
+    "fht_plan_upload", "fht_forward", "fht_forward_launch", "fht_batch_create",
+    "fht_batch_workspace_bytes", "fht_batch_num_launches", "fht_batch_run",
+    "fht_batch_run_launch", "fht_batch_destroy", "fht_plan_num_passes", "fht_plan_pass_tables",
+]
+
+FHT_U8, FHT_F32, FHT_F64 = 0, 1, 2
+FHT_SPLIT_S, FHT_SPLIT_T = 0, 1
+FHT_HDR_INTS = 32
+QUADRANTS = ("V+", "V-", "H+", "H-")
+
+STATUS = {0: "FHT_OK", -1: "FHT_EINVAL", -2: "FHT_EDTYPE", -3: "FHT_ENOMEM",
+          -4: "FHT_EHIP", -5: "FHT_EBUSY", -6: "FHT_ENODEV"}
+
+EXPORTED = (
+    "fht_status_string", "fht_plan_create", "fht_plan_destroy", "fht_plan_out_elems",
+    "fht_plan_out_offset", "fht_plan_workspace_bytes", "fht_plan_num_launches",
+    "fht_plan_upload", "fht_forward", "fht_forward_launch", "fht_batch_create",
+    "fht_batch_workspace_bytes", "fht_batch_num_launches", "fht_batch_run",
+    "fht_batch_run_launch", "fht_batch_destroy", "fht_plan_num_passes", "fht_plan_pass_tables",
+)
+
+
+class fht_schedule(ctypes.Structure):
+    _fields_ = [("s_tile", ctypes.c_int32), ("first_levels", ctypes.c_int32),
+                ("max_levels", ctypes.c_int32), ("lds_budget", ctypes.c_int32),
+                ("t_tile", ctypes.c_int32)]
+
+
+_vp, _i32, _u32, _i64, _sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32,
+                              ctypes.c_int64, ctypes.c_size_t)
+_pi32 = ctypes.POINTER(ctypes.c_int32)
+_ppi32 = ctypes.POINTER(_pi32)
+
+
+def _sig(name, res, *args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+_sig("fht_status_string", ctypes.c_char_p, _i32)
+_sig("fht_plan_create", _i32, ctypes.POINTER(_vp), _i32, _i32, _i32, _i32, _u32,
+     ctypes.POINTER(fht_schedule))
+_sig("fht_plan_destroy", None, _vp)
+_sig("fht_plan_out_elems", _sz, _vp)
+_sig("fht_plan_out_offset", _i64, _vp, _i32)
+_sig("fht_plan_workspace_bytes", _sz, _vp)
+_sig("fht_plan_num_launches", _i32, _vp)
+_sig("fht_plan_upload", _i32, _vp)
+_sig("fht_forward", _i32, _vp, _vp, _vp, _vp, _vp)
+_sig("fht_forward_launch", _i32, _vp, _i32, _vp, _vp, _vp, _vp)
+_sig("fht_batch_create", _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i32,
+     ctypes.POINTER(_vp), ctypes.POINTER(_vp))
+_sig("fht_batch_workspace_bytes", _sz, _vp)
+_sig("fht_batch_num_launches", _i32, _vp)
+_sig("fht_batch_run", _i32, _vp, _vp, _vp)
+_sig("fht_batch_run_launch", _i32, _vp, _i32, _vp, _vp)
+_sig("fht_batch_destroy", None, _vp)
+_sig("fht_plan_num_passes", _i32, _vp, _i32)
+_sig("fht_plan_pass_tables", _i32, _vp, _i32, _i32, _ppi32, _pi32, _ppi32, _pi32, _ppi32,
+     _pi32, _pi32)
+
+
+class FhtError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {STATUS.get(status, status)} ({fht_status_string(status)})")
+
+
+def _check(status: int, what: str) -> None:
+    if status != 0:
+        raise FhtError(status, what)
+
+
+# ----------------------------------------------------------------- C names
+
+def fht_status_string(status: int) -> str:
+    return _lib.fht_status_string(status).decode()
+
+
+def fht_plan_create(rows: int, cols: int, dtype: int, split: int, quadrant_mask: int = 15,
+                    schedule: fht_schedule | None = None) -> int:
+    h = _vp()
+    sched = ctypes.byref(schedule) if schedule is not None else None
+    _check(_lib.fht_plan_create(ctypes.byref(h), rows, cols, dtype, split, quadrant_mask, sched),
+           "fht_plan_create")
+    return h.value
+
+
+def fht_plan_destroy(plan: int) -> None:
+    _lib.fht_plan_destroy(plan)
+
+
+def fht_plan_out_elems(plan: int) -> int:
+    return _lib.fht_plan_out_elems(plan)
+
+
+def fht_plan_out_offset(plan: int, q: int) -> int:
+    return _lib.fht_plan_out_offset(plan, q)
+
+
+def fht_plan_workspace_bytes(plan: int) -> int:
+    return _lib.fht_plan_workspace_bytes(plan)
+
+
+def fht_plan_num_launches(plan: int) -> int:
+    return _lib.fht_plan_num_launches(plan)
+
+
+def fht_plan_upload(plan: int) -> None:
+    _check(_lib.fht_plan_upload(plan), "fht_plan_upload")
+
+
+def fht_forward(plan: int, d_img: int, d_out: int, d_ws: int | None, stream: int | None) -> None:
+    _check(_lib.fht_forward(plan, d_img, d_out, d_ws, stream), "fht_forward")
+
+
+def fht_forward_launch(plan: int, launch: int, d_img: int, d_out: int, d_ws: int | None,
+                       stream: int | None) -> None:
+    _check(_lib.fht_forward_launch(plan, launch, d_img, d_out, d_ws, stream), "fht_forward_launch")
+
+
+def fht_batch_create(plans: Sequence[int], d_imgs: Sequence[int], d_outs: Sequence[int]) -> int:
+    n = len(plans)
+    arr = ctypes.c_void_p * n
+    h = _vp()
+    _check(_lib.fht_batch_create(ctypes.byref(h), arr(*plans), n, arr(*d_imgs), arr(*d_outs)),
+           "fht_batch_create")
+    return h.value
+
+
+def fht_batch_workspace_bytes(batch: int) -> int:
+    return _lib.fht_batch_workspace_bytes(batch)
+
+
+def fht_batch_num_launches(batch: int) -> int:
+    return _lib.fht_batch_num_launches(batch)
+
+
+def fht_batch_run(batch: int, d_ws: int | None, stream: int | None) -> None:
+    _check(_lib.fht_batch_run(batch, d_ws, stream), "fht_batch_run")
+
+
+def fht_batch_run_launch(batch: int, launch: int, d_ws: int | None, stream: int | None) -> None:
+    _check(_lib.fht_batch_run_launch(batch, launch, d_ws, stream), "fht_batch_run_launch")
+
+
+def fht_batch_destroy(batch: int) -> None:
+    _lib.fht_batch_destroy(batch)
+
+
+def fht_plan_num_passes(plan: int, view: int) -> int:
+    return _lib.fht_plan_num_passes(plan, view)
+
+
+def fht_plan_pass_tables(plan: int, view: int, pass_idx: int) -> dict:
+    """Copies of one pass's host tables as NumPy arrays."""
+    hdrs, ops, items = _pi32(), _pi32(), _pi32()
+    nh, no, ni, s = _i32(), _i32(), _i32(), _i32()
+    _check(_lib.fht_plan_pass_tables(plan, view, pass_idx, ctypes.byref(hdrs), ctypes.byref(nh),
+                                     ctypes.byref(ops), ctypes.byref(no), ctypes.byref(items),
+                                     ctypes.byref(ni), ctypes.byref(s)), "fht_plan_pass_tables")
+
+    def arr(p, n, k):
+        if n == 0:
+            return np.zeros((0, k), dtype=np.int32)
+        return np.ctypeslib.as_array(p, shape=(n * k,)).reshape(n, k).copy()
+
+    return {"hdrs": arr(hdrs, nh.value, FHT_HDR_INTS), "ops": arr(ops, no.value, 4),
+            "items": arr(items, ni.value, 4), "s_tile": s.value}
+
+
+# ----------------------------------------------------------------- torch layer
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(dtype) -> int:
+    torch = _torch()
+    table = {"u8": FHT_U8, "uint8": FHT_U8, torch.uint8: FHT_U8,
+             "f32": FHT_F32, "float32": FHT_F32, torch.float32: FHT_F32,
+             "f64": FHT_F64, "float64": FHT_F64, torch.float64: FHT_F64}
+    if dtype not in table:
+        raise ValueError(f"unsupported dtype {dtype!r}")
+    return table[dtype]
+
+
+def _split_code(split) -> int:
+    table = {"S": FHT_SPLIT_S, "s": FHT_SPLIT_S, FHT_SPLIT_S: FHT_SPLIT_S,
+             "T": FHT_SPLIT_T, "t": FHT_SPLIT_T, FHT_SPLIT_T: FHT_SPLIT_T}
+    if split not in table:
+        raise ValueError(f"unknown split {split!r}")
+    return table[split]
+
+
+def _stream_handle(stream) -> int:
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+class Plan:
+    """A plan for rows x cols images (owns the C plan)."""
+
+    def __init__(self, rows: int, cols: int, dtype="u8", split="S", quadrants=(0, 1, 2, 3),
+                 schedule: dict | None = None):
+        torch = _torch()
+        self.rows, self.cols = int(rows), int(cols)
+        self.dtype_code = _dtype_code(dtype)
+        self.split = _split_code(split)
+        self.quadrants = tuple(sorted(set(int(q) for q in quadrants)))
+        mask = 0
+        for q in self.quadrants:
+            mask |= 1 << q
+        sched = fht_schedule(**schedule) if schedule else None
+        self.handle = fht_plan_create(self.rows, self.cols, self.dtype_code, self.split, mask, sched)
+        self.in_dtype = (torch.uint8, torch.float32, torch.float64)[self.dtype_code]
+        self.out_dtype = (torch.int32, torch.float32, torch.float64)[self.dtype_code]
+        self.out_elems = fht_plan_out_elems(self.handle)
+        self.ws_bytes = fht_plan_workspace_bytes(self.handle)
+        self.shapes = {q: ((self.rows, self.cols) if q < 2 else (self.cols, self.rows))
+                       for q in self.quadrants}
+        self.offsets = {q: fht_plan_out_offset(self.handle, q) for q in self.quadrants}
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            fht_plan_destroy(h)
+            self.handle = None
+
+    def new_out(self, device=None):
+        torch = _torch()
+        return torch.empty(self.out_elems, dtype=self.out_dtype, device=device or "cuda")
+
+    def new_ws(self, device=None):
+        torch = _torch()
+        return torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device or "cuda")
+
+    def split_out(self, out) -> list:
+        """Views of the flat output, one (W, H) tensor per selected quadrant."""
+        res = []
+        for q in self.quadrants:
+            W, H = self.shapes[q]
+            off = self.offsets[q]
+            res.append(out[off:off + W * H].view(W, H))
+        return res
+
+    def check_image(self, img) -> None:
+        if not img.is_cuda or not img.is_contiguous():
+            raise ValueError("image must be a contiguous device tensor")
+        if img.dtype != self.in_dtype or tuple(img.shape) != (self.rows, self.cols):
+            raise ValueError(f"image must be {self.in_dtype} of shape {(self.rows, self.cols)}")
+
+    def forward(self, img, out=None, ws=None, stream=None) -> list:
+        self.check_image(img)
+        if out is None:
+            out = self.new_out(img.device)
+        if ws is None and self.ws_bytes:
+            ws = self.new_ws(img.device)
+        if out.numel() < self.out_elems or out.dtype != self.out_dtype or not out.is_contiguous():
+            raise ValueError("output buffer has the wrong size or dtype")
+        if self.ws_bytes and ws.numel() * ws.element_size() < self.ws_bytes:
+            raise ValueError("workspace too small")
+        fht_forward(self.handle, img.data_ptr(), out.data_ptr(),
+                    ws.data_ptr() if ws is not None else None, _stream_handle(stream))
+        return self.split_out(out)
+
+
+class Batch:
+    """Many images (one plan each) run as one launch per fused pass."""
+
+    def __init__(self, plans: Sequence[Plan], imgs, outs):
+        if not (len(plans) == len(imgs) == len(outs)) or not plans:
+            raise ValueError("plans, images and outputs must be non-empty and of equal length")
+        for p, img, out in zip(plans, imgs, outs):
+            p.check_image(img)
+            if out.numel() < p.out_elems or out.dtype != p.out_dtype or not out.is_contiguous():
+                raise ValueError("output buffer has the wrong size or dtype")
+        self.plans = list(plans)      # keep the plans alive as long as the batch
+        self.imgs, self.outs = list(imgs), list(outs)
+        self.handle = fht_batch_create([p.handle for p in plans], [i.data_ptr() for i in imgs],
+                                       [o.data_ptr() for o in outs])
+        self.ws_bytes = fht_batch_workspace_bytes(self.handle)
+        self.num_launches = fht_batch_num_launches(self.handle)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            fht_batch_destroy(h)
+            self.handle = None
+
+    def new_ws(self, device=None):
+        torch = _torch()
+        return torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device or "cuda")
+
+    def run(self, ws, stream=None) -> None:
+        if self.ws_bytes and ws.numel() * ws.element_size() < self.ws_bytes:
+            raise ValueError("workspace too small")
+        fht_batch_run(self.handle, ws.data_ptr() if ws is not None else None,
+                      _stream_handle(stream))
+
+
+_plan_cache: dict = {}
+
+
+def hough(img, split="S", quadrants=(0, 1, 2, 3)) -> list:
+    """Transform one device image; returns one (W, H) tensor per quadrant."""
+    key = (tuple(img.shape), img.dtype, _split_code(split), tuple(quadrants))
+    plan = _plan_cache.get(key)
+    if plan is None:
+        plan = Plan(img.shape[0], img.shape[1], img.dtype, split, quadrants)
+        _plan_cache[key] = plan
+    return plan.forward(img)

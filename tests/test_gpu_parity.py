@@ -1,0 +1,160 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Integer images must match bit for bit (int32 outputs, int64 oracle).  Float
+images must satisfy |gpu - oracle_fp64| <= 1e-5 * (sum of |A| along the same
+line), the per-line bound the float path is held to.
+"""
+import numpy as np
+import pytest
+
+import workloads as WL
+from oracle import fht_oracle as O
+from oracle import native
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def F():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2411_07351_amd as F
+    return F
+
+
+def _gpu_hough(F, img_np, split, schedule=None, quadrants=(0, 1, 2, 3)):
+    img = torch.from_numpy(np.ascontiguousarray(img_np)).cuda()
+    plan = F.Plan(img.shape[0], img.shape[1], img.dtype, split, quadrants, schedule)
+    outs = plan.forward(img)
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() for o in outs]
+
+
+def _assert_float_close(got, ref, absref, tol=1e-5):
+    err = np.abs(got.astype(np.float64) - ref)
+    bound = tol * absref + 1e-30
+    bad = err > bound
+    assert not bad.any(), f"{bad.sum()} elements over tolerance, worst {np.max(err / bound):.3g}"
+
+
+@pytest.mark.parametrize("split", [0, 1])
+def test_config1_61x47_u8_bit_exact(F, split):
+    img = WL.uniform_u8(WL.rng_for(1), 61, 47)
+    got = _gpu_hough(F, img, split)
+    ref = O.hough4(img, split)
+    for q in range(4):
+        assert got[q].dtype == np.int32
+        assert (got[q] == ref[q]).all(), q
+
+
+@pytest.mark.parametrize("split", [0, 1])
+def test_shape_sweep_u8(F, split):
+    rng = WL.rng_for(0, salt=7)
+    shapes = [(1, 1), (1, 2), (2, 1), (1, 300), (300, 1), (2, 3), (3, 2), (5, 3), (13, 11),
+              (31, 33), (32, 32), (33, 31), (64, 65), (100, 37), (129, 257), (257, 129),
+              (200, 700)]
+    for R, C in shapes:
+        img = WL.uniform_u8(rng, R, C)
+        got = _gpu_hough(F, img, split)
+        ref = native.hough4_u8(img, split)
+        for q in range(4):
+            assert (got[q] == ref[q]).all(), (R, C, q)
+
+
+@pytest.mark.parametrize("sched", [
+    dict(s_tile=16, first_levels=2, max_levels=2, lds_budget=4096, t_tile=0),
+    dict(s_tile=32, first_levels=3, max_levels=3, lds_budget=16384, t_tile=4),
+    dict(s_tile=256, first_levels=4, max_levels=5, lds_budget=65536, t_tile=16),
+    dict(s_tile=64, first_levels=1, max_levels=1, lds_budget=65536, t_tile=0),
+])
+def test_schedules_u8(F, sched):
+    rng = WL.rng_for(0, salt=8)
+    for split in (0, 1):
+        for R, C in ((77, 45), (130, 17), (9, 300)):
+            img = WL.uniform_u8(rng, R, C)
+            got = _gpu_hough(F, img, split, sched)
+            ref = native.hough4_u8(img, split)
+            for q in range(4):
+                assert (got[q] == ref[q]).all(), (R, C, q, sched)
+
+
+def test_quadrant_subsets(F):
+    img = WL.uniform_u8(WL.rng_for(0, salt=9), 40, 23)
+    ref = native.hough4_u8(img, 1)
+    for qs in ((0,), (3,), (1, 2), (0, 2, 3)):
+        got = _gpu_hough(F, img, 1, quadrants=qs)
+        for g, q in zip(got, qs):
+            assert (g == ref[q]).all(), qs
+
+
+@pytest.mark.parametrize("split", [0, 1])
+def test_1024_equals_brady_yong(F, split):
+    # Sec. 3: at n = 2^q both variants coincide with Brady-Yong.
+    img = WL.edge_map(WL.rng_for(2, salt=1), 1024, 1024)
+    got = _gpu_hough(F, img, split)
+    for q, (A, sigma) in enumerate(O.quadrant_views(img)):
+        assert (got[q] == O.brady_yong(A, sigma)).all(), q
+
+
+@pytest.mark.parametrize("split", [0, 1])
+def test_config2_1021_full_vs_oracle(F, split):
+    # Two full 1021 x 1021 edge maps against the C oracle (about 4.3e9 adds each).
+    rng = WL.rng_for(2)
+    for _ in range(2 if split == 0 else 1):
+        img = WL.edge_map(rng, 1021, 1021)
+        got = _gpu_hough(F, img, split)
+        ref = native.hough4_u8(img, split)
+        for q in range(4):
+            assert (got[q] == ref[q]).all(), q
+
+
+def test_config4_f32_within_tolerance(F):
+    rng = WL.rng_for(4)
+    for split in (0, 1):
+        img = WL.normal_f32(rng, 384, 257)
+        got = _gpu_hough(F, img, split)
+        ref, absref = native.hough4_f64(img.astype(np.float64), split)
+        for q in range(4):
+            assert got[q].dtype == np.float32
+            _assert_float_close(got[q], ref[q], absref[q])
+
+
+def test_f64_small(F):
+    rng = WL.rng_for(4, salt=2)
+    img = rng.standard_normal((13, 11))
+    for split in (0, 1):
+        got = _gpu_hough(F, img, split)
+        ref, absref = native.hough4_f64(img, split)
+        for q in range(4):
+            _assert_float_close(got[q], ref[q], absref[q], tol=1e-12)
+
+
+def test_deterministic_and_invariants(F):
+    img = WL.edge_map(WL.rng_for(2, salt=3), 517, 300)
+    a = _gpu_hough(F, img, 0)
+    b = _gpu_hough(F, img, 0)
+    total = int(img.sum())
+    for q in range(4):
+        assert (a[q] == b[q]).all()
+        assert (a[q].sum(axis=1) == total).all()
+
+
+def test_batch_matches_plain(F):
+    rng = WL.rng_for(3, salt=1)
+    imgs_np = WL.ragged_edge_maps(rng, 12, 1, 300)
+    imgs_np[0] = WL.uniform_u8(rng, 1, 1)
+    imgs_np[1] = WL.uniform_u8(rng, 61, 47)
+    for split in (0, 1):
+        imgs = [torch.from_numpy(i).cuda() for i in imgs_np]
+        plans = [F.Plan(i.shape[0], i.shape[1], "u8", split) for i in imgs]
+        outs = [p.new_out() for p in plans]
+        batch = F.Batch(plans, imgs, outs)
+        ws = batch.new_ws()
+        batch.run(ws)
+        torch.cuda.synchronize()
+        for img_np, p, out in zip(imgs_np, plans, outs):
+            ref = native.hough4_u8(img_np, split)
+            for q, g in enumerate(p.split_out(out)):
+                assert (g.cpu().numpy() == ref[q]).all(), (img_np.shape, q)

@@ -1,0 +1,88 @@
+"""Host logic: the planner's tile programs, executed on the CPU, equal the oracle.
+
+No GPU: the tables are read through the C ABI (fht_plan_pass_tables) and run
+by a small interpreter with the kernel's semantics (tests/plan_interp.py).
+"""
+import numpy as np
+import pytest
+
+import paper_2411_07351_amd as F
+from oracle import fht_oracle as O
+from plan_interp import run_plan_tables
+
+SCHEDULES = [
+    None,
+    dict(s_tile=16, first_levels=2, max_levels=2, lds_budget=4096, t_tile=0),
+    dict(s_tile=32, first_levels=3, max_levels=3, lds_budget=16384, t_tile=4),
+    dict(s_tile=48, first_levels=1, max_levels=1, lds_budget=65536, t_tile=0),
+]
+
+
+def _plan(R, C, split, sched):
+    return F.fht_plan_create(R, C, F.FHT_U8, split, 15, F.fht_schedule(**sched) if sched else None)
+
+
+@pytest.mark.parametrize("split", [0, 1])
+@pytest.mark.parametrize("sched", SCHEDULES)
+def test_tables_equal_oracle(split, sched):
+    rng = np.random.default_rng(21)
+    shapes = [(1, 1), (1, 7), (7, 1), (2, 3), (5, 3), (13, 11), (17, 33), (61, 47), (64, 20),
+              (33, 70)]
+    for R, C in shapes:
+        img = rng.integers(0, 256, size=(R, C), dtype=np.uint8)
+        h = _plan(R, C, split, sched)
+        try:
+            ref = O.hough4(img, split)
+            for q in range(4):
+                got = run_plan_tables(h, img, q)
+                assert (got == ref[q]).all(), (R, C, q, sched)
+        finally:
+            F.fht_plan_destroy(h)
+
+
+@pytest.mark.parametrize("split", [0, 1])
+def test_tables_large_widths_sampled(split):
+    # Wide trees (several fused passes with the default schedule): compare full
+    # outputs of the interpreter with the C oracle.
+    from oracle import native
+    rng = np.random.default_rng(22)
+    for R, C in ((300, 9), (9, 257), (1021, 5)):
+        img = rng.integers(0, 256, size=(R, C), dtype=np.uint8)
+        h = F.fht_plan_create(R, C, F.FHT_U8, split, 15, None)
+        try:
+            ref = native.hough4_u8(img, split)
+            for q in range(4):
+                assert (run_plan_tables(h, img, q) == ref[q]).all(), (R, C, q)
+        finally:
+            F.fht_plan_destroy(h)
+
+
+def test_pass_structure_1021():
+    # Default schedule at 1021 lanes: a bottom pass of 5 levels and one top pass.
+    h = F.fht_plan_create(1021, 1021, F.FHT_U8, 0, 15, None)
+    try:
+        assert F.fht_plan_num_passes(h, 0) == 2
+        t0 = F.fht_plan_pass_tables(h, 0, 0)
+        assert (t0["hdrs"][:, 6] == 0).all() and (t0["hdrs"][:, 7] <= 5).all()
+        # two passes: one int32 intermediate per quadrant, 256-byte aligned
+        one = (1021 * 1021 * 4 + 255) // 256 * 256
+        assert F.fht_plan_workspace_bytes(h) == 4 * one
+    finally:
+        F.fht_plan_destroy(h)
+
+
+def test_invalid_arguments():
+    for args in ((0, 5), (5, 0), (-1, 5), (70000, 3)):
+        with pytest.raises(F.FhtError) as e:
+            F.fht_plan_create(args[0], args[1], F.FHT_U8, 0, 15, None)
+        assert e.value.status == -1
+    with pytest.raises(F.FhtError) as e:
+        F.fht_plan_create(4, 4, 7, 0, 15, None)
+    assert e.value.status == -2
+    for mask in (0, 16):
+        with pytest.raises(F.FhtError):
+            F.fht_plan_create(4, 4, F.FHT_U8, 0, mask, None)
+    with pytest.raises(F.FhtError):
+        F.fht_plan_create(4, 4, F.FHT_U8, 2, 15, None)
+    with pytest.raises(F.FhtError):
+        F.fht_plan_create(4, 4, F.FHT_U8, 0, 15, F.fht_schedule(s_tile=17))
