@@ -68,11 +68,14 @@ typedef struct fht_batch_s *fht_batch;
 /*
  * Tiling of the fused passes (not in the paper: the paper's recursion runs one
  * level at a time).  Zero in a field means "library default".
- *   s_tile      positions per work item (multiple of 16, <= 1024)
- *   first_levels  tree levels fused in the first pass (1..8)
- *   max_levels  tree levels fused in each later pass (1..10)
- *   lds_budget  LDS bytes a work item may use (<= 65536)
- *   t_tile      slope rows per work item in later passes (0 = choose)
+ *   s_tile        widest row window of a later pass, in positions (64, 128,
+ *                 192 or 256); the pass takes the largest position tile that fits
+ *   first_levels  tree levels fused in the first pass (1..6)
+ *   max_levels    tree levels fused in each later pass (1..16)
+ *   lds_budget    LDS bytes a work item may use (1024..65536)
+ *   t_tile        slope rows per work item in later passes (0 = choose)
+ *   s_tile_first  widest row window of the first pass (64..256, multiple of 64)
+ *   threads       threads per workgroup: 256, 512 or 1024
  */
 typedef struct {
     int32_t s_tile;
@@ -80,6 +83,8 @@ typedef struct {
     int32_t max_levels;
     int32_t lds_budget;
     int32_t t_tile;
+    int32_t s_tile_first;
+    int32_t threads;
 } fht_schedule;
 
 /* Human-readable name of a status code (static storage). */
@@ -142,7 +147,8 @@ fht_status fht_forward_launch(fht_plan plan, int32_t launch, const void *d_img, 
  *   plans  host array of n plans (each must outlive the batch)
  *   d_imgs host array of n device image pointers
  *   d_outs host array of n device output pointers (fht_plan_out_elems each)
- * Errors: FHT_EINVAL, FHT_EDTYPE (dtypes or splits differ), FHT_ENOMEM, FHT_EHIP.
+ * Errors: FHT_EINVAL (also: plans with different workgroup sizes), FHT_EDTYPE
+ * (dtypes or splits differ), FHT_ENOMEM, FHT_EHIP.
  */
 fht_status fht_batch_create(fht_batch *out, const fht_plan *plans, int32_t n,
                             const void *const *d_imgs, void *const *d_outs);
@@ -158,14 +164,16 @@ void fht_batch_destroy(fht_batch batch);
  * Quadrant view v = 0 (lanes are image rows) or 1 (lanes are image columns).
  * fht_plan_num_passes returns the number of fused passes of view v (or -1).
  * fht_plan_pass_tables returns pointers into the plan (valid while it lives):
- *   hdrs  n_progs x FHT_HDR_INTS ints: [0] first op, [1] loads, [2] stores,
- *         [3] steps, [4] LDS elements, [5] all ops, [6] lanes-in level,
- *         [7] lanes-out level, [8 + k] ops of step k
- *   ops   4 ints each: load {lds, src row, position offset, count},
- *         merge {lds dst, lds src0, lds src1, count} (dst = src0 + src1),
- *         store {lds src, dst row, 0, count}
+ *   hdrs  n_progs x FHT_HDR_INTS ints: [0] first entry, [1] loads, [2] stores,
+ *         [3] steps, [4] LDS elements, [5] all entries, [6] level in,
+ *         [7] height of the pass root, [8 + k] entries of step k,
+ *         [24] first pass: end of the padded load windows, [25] positions per item
+ *   ops   4 ints each, every entry covering k whole 64-position chunks:
+ *         load  {lds, src row, position offset, k}: lds[d+c] = src[row][(s0+off+c) mod H]
+ *         merge {lds dst, lds src0, lds src1, k}:  lds[d+c] = lds[a+c] + lds[b+c]
+ *         store {lds, dst row, limit, k}: dst[row][s0+c] = lds[d+c], c < limit, s0+c < H
  *   items 4 ints each: {program, 0, first position, 0}
- *   s_tile positions per item.
+ *   s_tile positions per item of this pass.
  */
 #define FHT_HDR_INTS 32
 int32_t fht_plan_num_passes(fht_plan plan, int32_t v);

@@ -55,7 +55,8 @@ EXPORTED = (
 class fht_schedule(ctypes.Structure):
     _fields_ = [("s_tile", ctypes.c_int32), ("first_levels", ctypes.c_int32),
                 ("max_levels", ctypes.c_int32), ("lds_budget", ctypes.c_int32),
-                ("t_tile", ctypes.c_int32)]
+                ("t_tile", ctypes.c_int32), ("s_tile_first", ctypes.c_int32),
+                ("threads", ctypes.c_int32)]
 
 
 _vp, _i32, _u32, _i64, _sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32,

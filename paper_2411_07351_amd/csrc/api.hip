@@ -81,6 +81,7 @@ struct fht_plan_s {
     std::vector<std::vector<int32_t>> items;  // per launch: {prog, job, s0, 0}
     std::vector<std::vector<int>> jobs_q;     // per launch: quadrant of each job slot
     std::vector<int> lds_bytes;               // per launch
+    int threads = 256;                        // per workgroup
     // prog_base[v][p]: index of the first program of view v, pass p.
     std::vector<int> prog_base[2];
     std::mutex mu;
@@ -139,6 +140,7 @@ struct fht_batch_s {
     std::vector<int32_t *> items;
     std::vector<int> n_items;
     std::vector<int> lds_bytes;
+    int threads = 256;
 
     ~fht_batch_s()
     {
@@ -183,13 +185,18 @@ fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, fht_dtype 
     fht::Schedule sc;
     if (sched) {
         if (sched->s_tile) sc.s_tile = sched->s_tile;
+        if (sched->s_tile_first) sc.s_tile_first = sched->s_tile_first;
+        if (sched->threads) sc.threads = sched->threads;
         if (sched->first_levels) sc.first_levels = sched->first_levels;
         if (sched->max_levels) sc.max_levels = sched->max_levels;
         if (sched->lds_budget) sc.lds_budget = sched->lds_budget;
         if (sched->t_tile) sc.t_tile = sched->t_tile;
     }
-    if (sc.s_tile < 16 || sc.s_tile > 1024 || sc.s_tile % 16 || sc.first_levels < 1 ||
-        sc.first_levels > 8 || sc.max_levels < 1 || sc.max_levels > 10 ||
+    if (sc.s_tile < fht::kChunk || sc.s_tile > fht::kMaxTarget || sc.s_tile % fht::kChunk ||
+        sc.s_tile_first < fht::kChunk || sc.s_tile_first > fht::kMaxTarget ||
+        sc.s_tile_first % fht::kChunk || sc.first_levels < 1 ||
+        (sc.threads != 256 && sc.threads != 512 && sc.threads != 1024) ||
+        sc.first_levels > fht::kMaxFirstLevels || sc.max_levels < 1 || sc.max_levels > fht::kMaxSteps ||
         sc.lds_budget < 1024 || sc.lds_budget > 65536 || sc.t_tile < 0 || sc.t_tile > 4096)
         return FHT_EINVAL;
 
@@ -201,13 +208,17 @@ fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, fht_dtype 
         p->dtype = dtype;
         p->split = split;
         p->qmask = quadrant_mask;
+        p->threads = sc.threads;
         const int eb = static_cast<int>(acc_bytes(dtype));
+        // uint8 images: first-pass sums of at most 64 lanes fit 16 bits in LDS.
+        const int first_eb = dtype == FHT_U8 ? 2 : eb;
         for (int v = 0; v < 2; ++v) {
             const bool used = quadrant_mask & (3u << (2 * v));
             if (!used) continue;
             const int W = v == 0 ? rows : cols, H = v == 0 ? cols : rows;
             std::string err;
-            if (!fht::plan_axis(W, H, static_cast<int>(split), eb, sc, &p->axis[v], &err)) {
+            if (!fht::plan_axis(W, H, static_cast<int>(split), first_eb, eb, sc, &p->axis[v],
+                                &err)) {
                 delete p;
                 return FHT_EINVAL;
             }
@@ -262,7 +273,7 @@ fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, fht_dtype 
                     p->items[l].push_back(ps.items[i + 2]);
                     p->items[l].push_back(0);
                 }
-                p->lds_bytes[l] = std::max(p->lds_bytes[l], ps.max_lds_elems * eb);
+                p->lds_bytes[l] = std::max(p->lds_bytes[l], ps.max_lds_elems * (l == 0 ? first_eb : eb));
             }
         }
     } catch (const std::bad_alloc &) {
@@ -327,7 +338,7 @@ static fht_status forward_one(fht_plan plan, const DevTables *t, size_t l, const
     }
     const int nitems = static_cast<int>(plan->items[l].size() / 4);
     const hipError_t e = fht::launch_pass(dt, l == 0, a, nitems, plan->lds_bytes[l],
-                                          static_cast<hipStream_t>(stream));
+                                          plan->threads, static_cast<hipStream_t>(stream));
     return hip_status(e);
 }
 
@@ -371,12 +382,15 @@ fht_status fht_batch_create(fht_batch *out, const fht_plan *plans, int32_t n,
     for (int i = 1; i < n; ++i)
         if (plans[i]->dtype != plans[0]->dtype || plans[i]->split != plans[0]->split)
             return FHT_EDTYPE;
+    for (int i = 1; i < n; ++i)
+        if (plans[i]->threads != plans[0]->threads) return FHT_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return FHT_ENODEV;
 
     fht_batch_s *b = new (std::nothrow) fht_batch_s;
     if (!b) return FHT_ENOMEM;
     b->dtype = plans[0]->dtype;
+    b->threads = plans[0]->threads;
     const size_t eb = acc_bytes(b->dtype);
     hipError_t e = hipGetDevice(&b->device);
     if (e != hipSuccess) {
@@ -491,7 +505,7 @@ static fht_status batch_one(fht_batch batch, size_t l, void *d_ws, void *stream)
     a.jobs = batch->jobs;
     a.ws = static_cast<char *>(d_ws);
     const hipError_t e = fht::launch_pass(static_cast<fht::Dt>(batch->dtype), l == 0, a,
-                                          batch->n_items[l], batch->lds_bytes[l],
+                                          batch->n_items[l], batch->lds_bytes[l], batch->threads,
                                           static_cast<hipStream_t>(stream));
     return hip_status(e);
 }
@@ -536,7 +550,7 @@ fht_status fht_plan_pass_tables(fht_plan plan, int32_t v, int32_t pass, const in
     if (n_ops) *n_ops = static_cast<int32_t>(ps.ops.size() / 4);
     if (items) *items = ps.items.data();
     if (n_items) *n_items = static_cast<int32_t>(ps.items.size() / 4);
-    if (s_tile) *s_tile = ax.S;
+    if (s_tile) *s_tile = ps.S;
     return FHT_OK;
 }
 

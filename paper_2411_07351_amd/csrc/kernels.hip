@@ -1,24 +1,61 @@
 // gfx950 kernels of the dyadic-pattern fast Hough transform.
 //
 // One launch executes one fused pass of Alg. 1 for many work items.  A work
-// item (one workgroup) runs a planner-made program: it loads the rows its
-// slope tile needs from HBM into LDS, runs the merge steps of Alg. 1 (row t
-// of a node = row t0 of the left child + row t1 of the right child rotated by
-// t - t1) entirely in LDS, and writes its output rows back.  The rotation is
-// folded into LDS addresses, so every merge is a contiguous vector add;
-// waves take whole rows and lanes take consecutive positions, which keeps LDS
-// accesses bank-conflict free and HBM accesses coalesced.  This is a
-// memory-bound integer or float add: no MFMA.
+// item (one workgroup of 4, 8 or 16 wavefronts) runs a planner-made program:
+// it loads the rows its slope tile needs into LDS, runs the merge steps of
+// Alg. 1 (row t of a node = row t0 of the left child + row t1 of the right
+// child rotated by t - t1) entirely in LDS, and writes its output rows back.
+// The rotation is folded into LDS addresses, so every merge is a contiguous
+// vector add over K whole 64-position chunks: one position per lane, which
+// keeps LDS accesses bank-conflict free and HBM accesses coalesced.  This is
+// a memory-bound integer or float add: no MFMA.
+//
+// Instruction economy.  K is fixed per program, so each row costs three
+// address additions and 3K LDS accesses.  Row descriptors reach a wavefront
+// 64 at a time through one vector load and are broadcast with readlane (a
+// scalar load per row would share the LDS wait counter and serialise the
+// rows); the next merge step's descriptors are fetched while the current step
+// runs.  Later passes load HBM rows straight into LDS (global_load_lds_dword),
+// all of a wavefront's rows in flight at once.
 #include "kernels.hpp"
 
 namespace fht {
 
 namespace {
 
+// Read-only tables, read through the constant address space so that the
+// compiler uses scalar loads for wave-uniform indices (item and header).
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T *p)
+{
+    return (cptr<T>)(p);
+}
+
+struct E4 { int x, y, z, w; };
+__device__ __forceinline__ E4 ld4(cptr<int32_t> t, int i)
+{
+    return E4{t[4 * i], t[4 * i + 1], t[4 * i + 2], t[4 * i + 3]};
+}
+
+__device__ __forceinline__ int rl(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
 template <bool TABLE>
 __device__ __forceinline__ JobDesc pick_job(const PassArgs &a, int j)
 {
-    if constexpr (TABLE) return a.jobs[j];
+    if constexpr (TABLE) {
+        cptr<JobDesc> p = as_const(a.jobs) + j;
+        JobDesc d;
+        d.src = p->src;
+        d.dst = p->dst;
+        d.H = p->H;
+        d.ld = p->ld;
+        d.flags = p->flags;
+        d.pad = 0;
+        return d;
+    }
     switch (j) {
     case 0: return a.inl[0];
     case 1: return a.inl[1];
@@ -27,114 +64,312 @@ __device__ __forceinline__ JobDesc pick_job(const PassArgs &a, int j)
     }
 }
 
-// TABLE: jobs come from a device table (batches) instead of kernel arguments.
-template <typename TSrc, typename TAcc, bool FROM_IMAGE, bool TABLE>
-__global__ void __launch_bounds__(kBlockThreads) fht_pass_kernel(PassArgs args)
+// (base + c) mod H for 0 <= base < H, c >= 0.
+__device__ __forceinline__ int wrap(int p, int H)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    TAcc *lds = reinterpret_cast<TAcc *>(smem_raw);
+    if (p >= H) p -= H;
+    if (p >= H) p %= H;
+    return p;
+}
 
-    const int4 item = args.items[blockIdx.x];
-    const int32_t *hdr = args.hdrs + static_cast<size_t>(item.x) * 32;
-    const int first = hdr[0], nload = hdr[1], nstore = hdr[2], nsteps = hdr[3];
-    const JobDesc job = pick_job<TABLE>(args, item.y);
+// Descriptors of this wavefront's entries g + NW * lane of a table of n entries.
+template <int NW>
+__device__ __forceinline__ int4 fetch_desc(const int4 *ent, int n, int g, int lane)
+{
+    const int idx = g + NW * lane;
+    return idx < n ? ent[idx] : make_int4(0, 0, 0, 0);
+}
+
+template <int NW>
+__device__ __forceinline__ int group_size(int n, int g)
+{
+    return min(64, (n - g + NW - 1) / NW);
+}
+
+// Merges of one group: entries {dst, src0, src1, K}, lds[dst + c] = lds[src0 + c] + lds[src1 + c].
+template <int K, typename TL>
+__device__ __forceinline__ void merge_group(TL *lds, const int4 &mine, int m, int lane)
+{
+    int j = 0;
+    for (; j + 2 <= m; j += 2) {
+        TL *d0 = lds + rl(mine.x, j) + lane, *d1 = lds + rl(mine.x, j + 1) + lane;
+        const TL *a0 = lds + rl(mine.y, j) + lane, *a1 = lds + rl(mine.y, j + 1) + lane;
+        const TL *b0 = lds + rl(mine.z, j) + lane, *b1 = lds + rl(mine.z, j + 1) + lane;
+        TL x0[K], y0[K], x1[K], y1[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            x0[k] = a0[64 * k];
+            y0[k] = b0[64 * k];
+            x1[k] = a1[64 * k];
+            y1[k] = b1[64 * k];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            d0[64 * k] = static_cast<TL>(x0[k] + y0[k]);
+            d1[64 * k] = static_cast<TL>(x1[k] + y1[k]);
+        }
+    }
+    if (j < m) {
+        TL *d0 = lds + rl(mine.x, j) + lane;
+        const TL *a0 = lds + rl(mine.y, j) + lane, *b0 = lds + rl(mine.z, j) + lane;
+        TL x0[K], y0[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            x0[k] = a0[64 * k];
+            y0[k] = b0[64 * k];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) d0[64 * k] = static_cast<TL>(x0[k] + y0[k]);
+    }
+}
+
+// Later-pass loads {dst, row, offset, K}: lds[dst + c] = src[row][(s0 + offset + c) mod H].
+// 32-bit elements go straight from HBM to LDS; float64 goes through registers.
+template <int K, int NW, typename TL>
+__device__ __forceinline__ void load_rows(TL *lds, const int4 *ent, int n, const TL *src, int H,
+                                          int s0, int wave, int lane)
+{
+    for (int g = wave; g < n; g += 64 * NW) {
+        const int4 mine = fetch_desc<NW>(ent, n, g, lane);
+        const int m = group_size<NW>(n, g);
+        for (int j = 0; j < m; ++j) {
+            int base = s0 + rl(mine.z, j);
+            if (base >= H) base %= H;
+            const TL *rowp = src + static_cast<size_t>(rl(mine.y, j)) * H;
+            TL *dst = lds + rl(mine.x, j);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const TL *gp = rowp + wrap(base + 64 * k + lane, H);
+                if constexpr (sizeof(TL) == 4) {
+                    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(gp),
+                                                     (__attribute__((address_space(3))) void *)(dst + 64 * k),
+                                                     4, 0, 0);
+                } else {
+                    dst[64 * k + lane] = *gp;
+                }
+            }
+        }
+    }
+}
+
+// First-pass loads: the lanes of the pass root (at most 64, one descriptor
+// {dst, lane, window start, K} each, in lane order) times their K-chunk
+// position windows, read from the image.  Lanes are image rows (positions
+// contiguous in memory) or image columns (lanes contiguous in memory); the
+// thread mapping follows the contiguous direction so that loads coalesce.
+//   rows: wavefront w takes lanes w + NW i, two lanes at a time
+//   cols: thread t takes lane t % XW and positions t / XW + k * (threads / XW)
+template <int K, int NW, typename TSrc, typename TL>
+__device__ __forceinline__ void load_image(TL *lds, const int4 *ent, int nl, int load_end,
+                                           const TSrc *img, const JobDesc &job, int s0, int wave,
+                                           int lane)
+{
     const int H = job.H;
-    const int s0 = item.z;
-    const int4 *ops = args.ops + first;
+    const bool mirror = job.flags & JF_MIRROR;
+    if (job.flags & JF_COLS) {
+        const int XW = nl <= 32 ? 32 : 64;
+        const int x = threadIdx.x % XW, pstep = 64 * NW / XW;
+        int4 mine = make_int4(0, 0, 0, 0);
+        if (x < nl) mine = ent[x];
+        const int wend = mine.z + 64 * K;
+        constexpr int U = 8;
+        for (int p0 = threadIdx.x / XW; p0 < load_end; p0 += pstep * U) {
+            TL v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int p = min(p0 + u * pstep, load_end - 1);
+                int y = wrap(s0 + p, H);
+                if (mirror && y != 0) y = H - y;
+                v[u] = (x < nl) ? static_cast<TL>(img[static_cast<size_t>(y) * job.ld + mine.y]) : TL(0);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int p = p0 + u * pstep;
+                if (x < nl && p < load_end && p >= mine.z && p < wend) lds[mine.x + p - mine.z] = v[u];
+            }
+        }
+    } else {
+        int4 mine = make_int4(0, 0, 0, 0);
+        if (lane < nl) mine = ent[lane];
+        for (int x0 = wave; x0 < nl; x0 += 2 * NW) {
+            const int x1 = min(x0 + NW, nl - 1);
+            const bool two = x0 + NW < nl;
+            TL v[2 * K];
+#pragma unroll
+            for (int q = 0; q < 2 * K; ++q) {
+                const int x = q < K ? x0 : x1;
+                const int k = q < K ? q : q - K;
+                int base = s0 + rl(mine.z, x);
+                if (base >= H) base %= H;
+                int y = wrap(base + 64 * k + lane, H);
+                if (mirror && y != 0) y = H - y;
+                v[q] = static_cast<TL>(img[static_cast<size_t>(rl(mine.y, x)) * job.ld + y]);
+            }
+#pragma unroll
+            for (int q = 0; q < 2 * K; ++q) {
+                const int x = q < K ? x0 : x1;
+                const int k = q < K ? q : q - K;
+                if (q < K || two) lds[rl(mine.x, x) + 64 * k + lane] = v[q];
+            }
+        }
+    }
+}
 
+// Stores {src, row, limit, K}: dst[row][s0 + c] = lds[src + c] for c < limit
+// and s0 + c < H; the final output of a negative-slope quadrant is written
+// back in un-mirrored position order.
+template <int K, int NW, typename TL, typename TAcc>
+__device__ __forceinline__ void store_rows(const TL *lds, const int4 *ent, int n, TAcc *dst, int H,
+                                           int s0, bool unmirror, int wave, int lane)
+{
+    for (int g = wave; g < n; g += 64 * NW) {
+        const int4 mine = fetch_desc<NW>(ent, n, g, lane);
+        const int m = group_size<NW>(n, g);
+        for (int j = 0; j < m; ++j) {
+            const int lim = min(rl(mine.z, j), H - s0);
+            const TL *srcp = lds + rl(mine.x, j) + lane;
+            TAcc *rowp = dst + static_cast<size_t>(rl(mine.y, j)) * H;
+            TL v[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[k] = srcp[64 * k];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int c = 64 * k + lane;
+                if (c < lim) {
+                    const int s = s0 + c;
+                    rowp[(unmirror && s != 0) ? H - s : s] = static_cast<TAcc>(v[k]);
+                }
+            }
+        }
+    }
+}
+
+template <int NT, int K, typename TSrc, typename TL, typename TAcc, bool FROM_IMAGE>
+__device__ __forceinline__ void run_item(TL *lds, cptr<int32_t> hdr, const int4 *ent,
+                                         const JobDesc &job, const char *src, char *dst, int s0)
+{
+    constexpr int NW = NT / 64;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    constexpr int nw = kBlockThreads / 64;
+    const int nload = hdr[1], nstore = hdr[2], nsteps = hdr[3];
+    const int H = job.H;
+
+    // Descriptors of the first merge step, fetched before the loads.
+    const int4 *step_ent = ent + nload;
+    int cnt = nsteps > 0 ? hdr[8] : 0;
+    int4 cur = fetch_desc<NW>(step_ent, cnt, wave, lane);
+
+    if constexpr (FROM_IMAGE) {
+        load_image<K, NW, TSrc, TL>(lds, ent, nload, hdr[24], reinterpret_cast<const TSrc *>(src),
+                                    job, s0, wave, lane);
+    } else {
+        load_rows<K, NW, TL>(lds, ent, nload, reinterpret_cast<const TL *>(src), H, s0, wave,
+                             lane);
+        __builtin_amdgcn_s_waitcnt(0);  // direct-to-LDS loads have landed
+    }
+
+    for (int k = 0; k < nsteps; ++k) {
+        __syncthreads();
+        const int4 *next_ent = step_ent + cnt;
+        const int next_cnt = k + 1 < nsteps ? hdr[8 + k + 1] : 0;
+        const int4 nxt = fetch_desc<NW>(next_ent, next_cnt, wave, lane);
+        if (wave < cnt) merge_group<K, TL>(lds, cur, group_size<NW>(cnt, wave), lane);
+        for (int g = wave + 64 * NW; g < cnt; g += 64 * NW)
+            merge_group<K, TL>(lds, fetch_desc<NW>(step_ent, cnt, g, lane), group_size<NW>(cnt, g),
+                               lane);
+        step_ent = next_ent;
+        cnt = next_cnt;
+        cur = nxt;
+    }
+    __syncthreads();
+
+    const bool unmirror = (job.flags & JF_FINAL) && (job.flags & JF_MIRROR);
+    store_rows<K, NW, TL, TAcc>(lds, step_ent, nstore, reinterpret_cast<TAcc *>(dst), H, s0,
+                                unmirror, wave, lane);
+}
+
+// TL: LDS element type (16-bit for the first pass of uint8 images, whose
+// sums of at most 64 lanes stay below 2^16; otherwise the accumulator type).
+// TABLE: jobs come from a device table (batches) instead of kernel arguments.
+//
+// Workgroup b runs item (b mod 8) * ceil(n / 8) + b / 8: workgroups are
+// dealt to the eight XCDs round robin, so this gives each XCD a contiguous
+// range of items and neighbouring tiles, which read overlapping rows, share
+// an L2.
+template <int NT, typename TSrc, typename TL, typename TAcc, bool FROM_IMAGE, bool TABLE>
+__global__ void __launch_bounds__(NT) fht_pass_kernel(PassArgs args, int n_items)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    TL *lds = reinterpret_cast<TL *>(smem_raw);
+
+    const int per_xcd = (n_items + 7) / 8;
+    const int it = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (it >= n_items) return;
+    const E4 item = ld4(as_const(reinterpret_cast<const int32_t *>(args.items)), it);
+    cptr<int32_t> hdr = as_const(args.hdrs) + static_cast<size_t>(item.x) * 32;
+    const JobDesc job = pick_job<TABLE>(args, item.y);
+    const int4 *ent = args.ops + hdr[0];
 
     const char *src = static_cast<const char *>(job.src);
     if (job.flags & JF_SRC_WS) src = args.ws + reinterpret_cast<uintptr_t>(job.src);
     char *dst = static_cast<char *>(job.dst);
     if (job.flags & JF_DST_WS) dst = args.ws + reinterpret_cast<uintptr_t>(job.dst);
 
-    // Load phase: lds[d + c] = src[row][(s0 + off + c) mod H].
-    for (int i = wave; i < nload; i += nw) {
-        const int4 op = ops[i];
-        int base = s0 + op.z;
-        if (base >= H) base %= H;
-        for (int c = lane; c < op.w; c += 64) {
-            int pos = base + c;
-            if (pos >= H) pos -= H;
-            if (pos >= H) pos %= H;
-            TAcc v;
-            if constexpr (FROM_IMAGE) {
-                int y = pos;
-                if ((job.flags & JF_MIRROR) && y != 0) y = H - y;
-                const size_t addr = (job.flags & JF_COLS)
-                                        ? static_cast<size_t>(y) * job.ld + op.y
-                                        : static_cast<size_t>(op.y) * job.ld + y;
-                v = static_cast<TAcc>(reinterpret_cast<const TSrc *>(src)[addr]);
-            } else {
-                v = reinterpret_cast<const TAcc *>(src)[static_cast<size_t>(op.y) * H + pos];
-            }
-            lds[op.x + c] = v;
-        }
+    switch (hdr[26]) {
+    case 1: run_item<NT, 1, TSrc, TL, TAcc, FROM_IMAGE>(lds, hdr, ent, job, src, dst, item.z); break;
+    case 2: run_item<NT, 2, TSrc, TL, TAcc, FROM_IMAGE>(lds, hdr, ent, job, src, dst, item.z); break;
+    case 3: run_item<NT, 3, TSrc, TL, TAcc, FROM_IMAGE>(lds, hdr, ent, job, src, dst, item.z); break;
+    default: run_item<NT, 4, TSrc, TL, TAcc, FROM_IMAGE>(lds, hdr, ent, job, src, dst, item.z); break;
     }
+}
 
-    // Merge steps of Alg. 1: lds[d + c] = lds[a + c] + lds[b + c].
-    int k0 = nload;
-    for (int k = 0; k < nsteps; ++k) {
-        __syncthreads();
-        const int cnt = hdr[8 + k];
-        for (int i = wave; i < cnt; i += nw) {
-            const int4 op = ops[k0 + i];
-            for (int c = lane; c < op.w; c += 64)
-                lds[op.x + c] = lds[op.y + c] + lds[op.z + c];
-        }
-        k0 += cnt;
+template <int NT, typename TSrc, typename TFirst, typename TAcc>
+hipError_t launch_nt(bool from_image, const PassArgs &args, int n_items, int lds_bytes,
+                     hipStream_t stream)
+{
+    const dim3 grid((n_items + 7) / 8 * 8), block(NT);
+    const bool table = args.jobs != nullptr;
+    if (from_image) {
+        if (table)
+            fht_pass_kernel<NT, TSrc, TFirst, TAcc, true, true><<<grid, block, lds_bytes, stream>>>(args, n_items);
+        else
+            fht_pass_kernel<NT, TSrc, TFirst, TAcc, true, false><<<grid, block, lds_bytes, stream>>>(args, n_items);
+    } else {
+        if (table)
+            fht_pass_kernel<NT, TAcc, TAcc, TAcc, false, true><<<grid, block, lds_bytes, stream>>>(args, n_items);
+        else
+            fht_pass_kernel<NT, TAcc, TAcc, TAcc, false, false><<<grid, block, lds_bytes, stream>>>(args, n_items);
     }
-    __syncthreads();
+    return hipGetLastError();
+}
 
-    // Store phase: dst[row][s0 + c] for s0 + c < H (final output un-mirrored).
-    const int limit = H - s0;
-    const bool unmirror = (job.flags & JF_FINAL) && (job.flags & JF_MIRROR);
-    TAcc *out = reinterpret_cast<TAcc *>(dst);
-    for (int i = wave; i < nstore; i += nw) {
-        const int4 op = ops[k0 + i];
-        const int n = op.w < limit ? op.w : limit;
-        TAcc *row = out + static_cast<size_t>(op.y) * H;
-        for (int c = lane; c < n; c += 64) {
-            int s = s0 + c;
-            if (unmirror && s != 0) s = H - s;
-            row[s] = lds[op.x + c];
-        }
+template <typename TSrc, typename TFirst, typename TAcc>
+hipError_t launch_typed(bool from_image, const PassArgs &args, int n_items, int lds_bytes,
+                        int threads, hipStream_t stream)
+{
+    switch (threads) {
+    case 512: return launch_nt<512, TSrc, TFirst, TAcc>(from_image, args, n_items, lds_bytes, stream);
+    case 1024: return launch_nt<1024, TSrc, TFirst, TAcc>(from_image, args, n_items, lds_bytes, stream);
+    default: return launch_nt<256, TSrc, TFirst, TAcc>(from_image, args, n_items, lds_bytes, stream);
     }
 }
 
 }  // namespace
 
-template <typename TSrc, typename TAcc>
-hipError_t launch_typed(bool from_image, const PassArgs &args, int n_items, int lds_bytes,
-                        hipStream_t stream)
-{
-    const dim3 grid(n_items), block(kBlockThreads);
-    const bool table = args.jobs != nullptr;
-    if (from_image) {
-        if (table)
-            fht_pass_kernel<TSrc, TAcc, true, true><<<grid, block, lds_bytes, stream>>>(args);
-        else
-            fht_pass_kernel<TSrc, TAcc, true, false><<<grid, block, lds_bytes, stream>>>(args);
-    } else {
-        if (table)
-            fht_pass_kernel<TAcc, TAcc, false, true><<<grid, block, lds_bytes, stream>>>(args);
-        else
-            fht_pass_kernel<TAcc, TAcc, false, false><<<grid, block, lds_bytes, stream>>>(args);
-    }
-    return hipGetLastError();
-}
-
 hipError_t launch_pass(Dt dt, bool from_image, const PassArgs &args, int n_items,
-                       int lds_bytes, hipStream_t stream)
+                       int lds_bytes, int threads, hipStream_t stream)
 {
     if (n_items <= 0) return hipSuccess;
     switch (dt) {
-    case Dt::U8: return launch_typed<uint8_t, int32_t>(from_image, args, n_items, lds_bytes, stream);
-    case Dt::F32: return launch_typed<float, float>(from_image, args, n_items, lds_bytes, stream);
-    case Dt::F64: return launch_typed<double, double>(from_image, args, n_items, lds_bytes, stream);
+    case Dt::U8:
+        return launch_typed<uint8_t, uint16_t, int32_t>(from_image, args, n_items, lds_bytes,
+                                                        threads, stream);
+    case Dt::F32:
+        return launch_typed<float, float, float>(from_image, args, n_items, lds_bytes, threads,
+                                                 stream);
+    case Dt::F64:
+        return launch_typed<double, double, double>(from_image, args, n_items, lds_bytes, threads,
+                                                    stream);
     }
     return hipErrorInvalidValue;
 }

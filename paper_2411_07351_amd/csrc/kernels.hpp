@@ -26,7 +26,6 @@ enum : int32_t {
 };
 
 constexpr int kInlineJobs = 4;
-constexpr int kBlockThreads = 256;
 
 struct PassArgs {
     const int4 *items;     // {program, job, first position, 0}
@@ -39,10 +38,11 @@ struct PassArgs {
 
 enum class Dt { U8 = 0, F32 = 1, F64 = 2 };
 
-// Enqueues one fused pass of `n_items` work items.  from_image selects the
-// first-pass loader (reads the image of dtype dt), otherwise the pass reads
-// accumulator rows.  Returns the launch status.
+// Enqueues one fused pass of `n_items` work items with `threads` (256, 512
+// or 1024) threads per workgroup.  from_image selects the first-pass loader
+// (reads the image of dtype dt), otherwise the pass reads accumulator rows.
+// Returns the launch status.
 hipError_t launch_pass(Dt dt, bool from_image, const PassArgs &args, int n_items,
-                       int lds_bytes, hipStream_t stream);
+                       int lds_bytes, int threads, hipStream_t stream);
 
 }  // namespace fht

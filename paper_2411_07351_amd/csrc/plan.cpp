@@ -5,16 +5,21 @@
 // maximal subtrees of height <= lin; level 0 is the input lanes) to those of
 // the frontier of level lout, entirely in LDS, one work item per
 // (pass root, slope tile, position tile).  For each work item the planner
-// emits a straight-line program of row operations:
-//   load   lds[d + c]  = src[row][(s0 + off + c) mod H]          c < count
-//   merge  lds[d + c]  = lds[a + c] + lds[b + c]                   c < count
-//   store  dst[row][s0 + c] = lds[d + c]                           c < count, s0 + c < H
+// emits a straight-line program of row entries (k = 64-position chunks):
+//   load   lds[d + c] = src[row][(s0 + off + c) mod H]             c < 64 k
+//   merge  lds[d + c] = lds[a + c] + lds[b + c]                      c < 64 k
+//   store  dst[row][s0 + c] = lds[d + c]                 c < min(64 k, lim), s0 + c < H
 // A merge is the vector operation of Alg. 1: row t of a node is row t0 of its
 // left child plus row t1 of its right child rotated by r = t - t1, with
 // t_P = [t (w_P - 1)/(w - 1)] rounded half to even.  Rotation is folded into
-// the LDS address of the right operand: every node stores a window of
+// the LDS address of the right operand: every node keeps a window of
 // positions [lo, hi) relative to the tile start, and the right child's window
 // is widened by the range of r over the rows the tile needs.
+//
+// Rows are stored with a stride rounded up to whole chunks and every entry
+// runs whole chunks: the positions past a window are computed but never
+// read back.  A right child carries the few positions of slack that the
+// shifted whole-chunk reads of its last row need, so they stay inside it.
 #include "plan.hpp"
 
 #include <algorithm>
@@ -79,6 +84,8 @@ Tree make_tree(int W, int split)
 
 namespace {
 
+int chunks_of(int width) { return (width + kChunk - 1) / kChunk; }
+
 struct Block {
     int node;
     int ulo, uhi;     // rows of the node this tile needs (inclusive)
@@ -87,13 +94,19 @@ struct Block {
     int last;         // last step that reads it
     int lb = -1, rb = -1;
     int off = -1;     // LDS element offset
+    int overrun = 0;  // positions a merge reads past the end of the last row
+    int row_stride = 0;
     int width() const { return hi - lo; }
     int rows() const { return uhi - ulo + 1; }
+    int stride() const { return row_stride; }
+    int size() const { return rows() * stride() + overrun; }
 };
 
 struct TileBuilder {
     const Tree &tr;
     int lin;
+    int K;            // chunks every entry of the tile covers
+    int stride;       // LDS row stride: K chunks plus a bank-skew pad
     std::vector<Block> blocks;
 
     int need(int ni, int ulo, int uhi, int lo, int hi)
@@ -101,6 +114,7 @@ struct TileBuilder {
         const Node &n = tr.nodes[ni];
         const int b = static_cast<int>(blocks.size());
         blocks.push_back(Block{ni, ulo, uhi, lo, hi, 0, -1});
+        blocks[b].row_stride = stride;
         if (n.height <= lin) return b;
         blocks[b].step = n.height - lin;
         const int w = n.w, w0 = n.w0, w1 = w - w0;
@@ -114,6 +128,11 @@ struct TileBuilder {
         blocks[rb].last = blocks[b].step;
         blocks[b].lb = lb;
         blocks[b].rb = rb;
+        // A merge reads K whole chunks of the right child, starting up to
+        // (uhi - t1hi) - (ulo - t1lo) positions into a row.
+        Block &R = blocks[rb];
+        const int reach = (uhi - t1hi) - (ulo - t1lo) + K * kChunk;
+        R.overrun = std::max(R.overrun, reach - R.stride());
         return b;
     }
 };
@@ -135,7 +154,7 @@ int place(std::vector<Block> &blocks)
                                   [&](const Live &l) { return l.last < blk.step; }),
                    live.end());
         std::sort(live.begin(), live.end(), [](const Live &x, const Live &y) { return x.off < y.off; });
-        const int size = blk.rows() * blk.width();
+        const int size = blk.size();
         int pos = 0;
         for (const Live &l : live) {
             if (l.off - pos >= size) break;
@@ -159,10 +178,20 @@ void collect_frontier(const Tree &tr, int ni, int level, std::vector<int> *out)
     collect_frontier(tr, n.right, level, out);
 }
 
-// Emits one tile program for rows [ta, tb) of pass root `root`.
-void emit_tile(const Tree &tr, int root, int ta, int tb, int lin, int S, Pass *pass)
+// Emits one tile program for rows [ta, tb) of pass root `root`.  Every entry
+// covers the same K chunks (the pass's target width); rows are stored with a
+// stride of K chunks plus `pad` elements, which skews consecutive rows across
+// LDS banks.
+//
+// Entry formats (4 ints each):
+//   load   {lds row start, source row, position offset, K}; in the first
+//          pass there is one per lane, in lane order
+//   merge  {lds dst, lds src0, lds src1, K}
+//   store  {lds row start, destination row, position limit, K}
+void emit_tile(const Tree &tr, int root, int ta, int tb, int lin, int S, int K, int pad,
+               Pass *pass)
 {
-    TileBuilder tb_{tr, lin, {}};
+    TileBuilder tb_{tr, lin, K, K * kChunk + pad, {}};
     const int rb = tb_.need(root, ta, tb - 1, 0, S);
     std::vector<Block> &bl = tb_.blocks;
     const int nsteps = std::max(0, tr.nodes[root].height - lin);
@@ -177,12 +206,15 @@ void emit_tile(const Tree &tr, int root, int ta, int tb, int lin, int S, Pass *p
         pass->ops.push_back(b);
         pass->ops.push_back(n);
     };
-    int nload = 0;
+    int nload = 0, load_end = 0, widest = 0;
     for (const Block &b : bl) {
+        widest = std::max(widest, b.width());
         if (b.step != 0) continue;
         const Node &n = tr.nodes[b.node];
-        for (int u = b.ulo; u <= b.uhi; ++u, ++nload)
-            push(b.off + (u - b.ulo) * b.width(), n.a + u, b.lo, b.width());
+        for (int u = b.ulo; u <= b.uhi; ++u, ++nload) {
+            push(b.off + (u - b.ulo) * b.stride(), n.a + u, b.lo, K);
+            load_end = std::max(load_end, b.lo + K * kChunk);
+        }
     }
     for (int k = 1; k <= nsteps; ++k) {
         int cnt = 0;
@@ -195,10 +227,9 @@ void emit_tile(const Tree &tr, int root, int ta, int tb, int lin, int S, Pass *p
                 const int t0 = static_cast<int>(round_half_even(int64_t(u) * (w0 - 1), w - 1));
                 const int t1 = static_cast<int>(round_half_even(int64_t(u) * (w1 - 1), w - 1));
                 const int r = u - t1;
-                push(b.off + (u - b.ulo) * b.width(),
-                     L.off + (t0 - L.ulo) * L.width() + (b.lo - L.lo),
-                     R.off + (t1 - R.ulo) * R.width() + (b.lo + r - R.lo),
-                     b.width());
+                push(b.off + (u - b.ulo) * b.stride(),
+                     L.off + (t0 - L.ulo) * L.stride() + (b.lo - L.lo),
+                     R.off + (t1 - R.ulo) * R.stride() + (b.lo + r - R.lo), K);
             }
         }
         hdr[8 + k - 1] = cnt;
@@ -208,7 +239,7 @@ void emit_tile(const Tree &tr, int root, int ta, int tb, int lin, int S, Pass *p
         const Block &b = bl[rb];
         const Node &n = tr.nodes[b.node];
         for (int u = b.ulo; u <= b.uhi; ++u, ++nstore)
-            push(b.off + (u - b.ulo) * b.width(), n.a + u, 0, b.width());
+            push(b.off + (u - b.ulo) * b.stride(), n.a + u, S, K);
     }
     hdr[0] = first;
     hdr[1] = nload;
@@ -218,15 +249,22 @@ void emit_tile(const Tree &tr, int root, int ta, int tb, int lin, int S, Pass *p
     hdr[5] = static_cast<int>(pass->ops.size() / 4) - first;
     hdr[6] = lin;
     hdr[7] = tr.nodes[root].height;
+    hdr[kHdrLoadEnd] = load_end;
+    hdr[kHdrSTile] = S;
+    hdr[kHdrChunks] = K;
     pass->hdrs.insert(pass->hdrs.end(), hdr, hdr + kHdrInts);
     pass->max_lds_elems = std::max(pass->max_lds_elems, lds);
+    pass->widest = std::max(pass->widest, widest);
+    if (widest > K * kChunk || K > kMaxChunks) pass->fits = false;
 }
 
-bool build_pass(const Tree &tr, int lin, int lout, int T, int S, int H, Pass *pass)
+void build_pass(const Tree &tr, int lin, int lout, int T, int S, int K, int pad, int H,
+                Pass *pass)
 {
     pass->lin = lin;
     pass->lout = lout;
     pass->t_tile = T;
+    pass->S = S;
     std::vector<int> roots;
     collect_frontier(tr, 0, lout, &roots);
     for (int r : roots) {
@@ -234,7 +272,7 @@ bool build_pass(const Tree &tr, int lin, int lout, int T, int S, int H, Pass *pa
         const int tt = (T <= 0) ? w : T;
         for (int ta = 0; ta < w; ta += tt) {
             const int prog = static_cast<int>(pass->hdrs.size() / kHdrInts);
-            emit_tile(tr, r, ta, std::min(w, ta + tt), lin, S, pass);
+            emit_tile(tr, r, ta, std::min(w, ta + tt), lin, S, K, pad, pass);
             for (int s0 = 0; s0 < H; s0 += S) {
                 pass->items.push_back(prog);
                 pass->items.push_back(0);
@@ -243,15 +281,31 @@ bool build_pass(const Tree &tr, int lin, int lout, int T, int S, int H, Pass *pa
             }
         }
     }
-    return true;
+}
+
+// Builds the pass with the largest position tile whose widest window still
+// fits the target width (windows are the tile plus a spread that depends on
+// the slope tile only).
+void build_pass_fitted(const Tree &tr, int lin, int lout, int T, int target, int pad, int H,
+                       Pass *out)
+{
+    // Windows are S plus a spread that does not depend on S: probe it with
+    // S = 16 (so that the probe itself fits), then pick the largest S.
+    const int Kmax = target / kChunk;
+    Pass probe;
+    build_pass(tr, lin, lout, T, 16, Kmax + 64, pad, H, &probe);
+    const int spread = probe.widest - 16;
+    const int S = std::min(H, std::max(16, target - spread));
+    const int K = std::max(1, chunks_of(S + spread));
+    build_pass(tr, lin, lout, T, S, K, pad, H, out);
 }
 
 }  // namespace
 
-bool plan_axis(int W, int H, int split, int elem_bytes, const Schedule &sched,
+bool plan_axis(int W, int H, int split, int first_bytes, int rest_bytes, const Schedule &sched,
                AxisPlan *out, std::string *err)
 {
-    if (W < 1 || H < 1 || (split != 0 && split != 1) || elem_bytes <= 0) {
+    if (W < 1 || H < 1 || (split != 0 && split != 1) || first_bytes <= 0 || rest_bytes <= 0) {
         if (err) *err = "bad axis arguments";
         return false;
     }
@@ -260,24 +314,30 @@ bool plan_axis(int W, int H, int split, int elem_bytes, const Schedule &sched,
     out->W = W;
     out->H = H;
     out->split = split;
-    out->S = std::min(sched.s_tile, (H + 15) / 16 * 16);
     out->passes.clear();
-    const int budget_elems = sched.lds_budget / elem_bytes;
     int lin = 0;
     do {
-        const int maxlv = (lin == 0) ? sched.first_levels : sched.max_levels;
+        const int eb = lin == 0 ? first_bytes : rest_bytes;
+        const int budget_elems = sched.lds_budget / eb;
+        const int pad = eb == 2 ? 2 : 1;  // one 32-bit bank (two for 64-bit elements)
+        const int maxlv = (lin == 0) ? std::min(sched.first_levels, kMaxFirstLevels)
+                                     : std::min(sched.max_levels, kMaxSteps);
+        const int target = (lin == 0) ? sched.s_tile_first : sched.s_tile;
         bool found = false;
         Pass best;
         const int hi = std::min(L, lin + maxlv);
         const int lo = (L > lin) ? lin + 1 : lin;
         for (int lout = hi; lout >= lo && !found; --lout) {
+            // The first pass takes whole roots (at most 64 lanes, loaded as one
+            // lane x window rectangle).
             std::vector<int> tiles;
-            if (sched.t_tile > 0) tiles = {sched.t_tile};
+            if (lin == 0) tiles = {0};
+            else if (sched.t_tile > 0) tiles = {sched.t_tile};
             else tiles = {0, 64, 32, 16, 8, 4};
             for (int T : tiles) {
                 Pass p;
-                build_pass(tr, lin, lout, T, out->S, H, &p);
-                if (p.max_lds_elems <= budget_elems) {
+                build_pass_fitted(tr, lin, lout, T, target, pad, H, &p);
+                if (p.fits && p.max_lds_elems <= budget_elems) {
                     best = std::move(p);
                     found = true;
                     break;

@@ -9,7 +9,14 @@
 namespace fht {
 
 constexpr int kHdrInts = 32;     // ints per tile-program header
-constexpr int kMaxSteps = 24;    // header slots for per-step op counts (8 + k < 32)
+constexpr int kMaxSteps = 16;    // header slots 8 .. 23: entries of each merge step
+constexpr int kHdrLoadEnd = 24;  // first pass: largest end of a lane's padded load window
+constexpr int kHdrSTile = 25;    // positions per work item of this pass
+constexpr int kHdrChunks = 26;   // chunks K every entry of the program covers
+constexpr int kChunk = 64;       // positions per chunk (one wavefront access)
+constexpr int kMaxFirstLevels = 6;  // first-pass roots have at most 64 lanes
+constexpr int kMaxTarget = 256;     // widest row window a schedule may ask for
+constexpr int kMaxChunks = 4;       // chunks per entry the kernels are built for
 
 // [.] of Alg. 1: nearest integer to num / den (num >= 0, den > 0), ties to even.
 int64_t round_half_even(int64_t num, int64_t den);
@@ -33,12 +40,16 @@ struct Tree {
 
 Tree make_tree(int W, int split);
 
+// Row windows are tiled in 64-position chunks; a pass picks the largest
+// position tile whose widest window fits its target width.
 struct Schedule {
-    int s_tile = 128;
+    int s_tile = 128;         // target window width, later passes
+    int s_tile_first = 192;   // target window width, first pass
     int first_levels = 5;
     int max_levels = 6;
     int lds_budget = 64 * 1024;
     int t_tile = 0;           // 0: try 64, 32, 16, 8
+    int threads = 256;        // threads per workgroup: 256, 512 or 1024
 };
 
 // One fused pass: from the frontier of level lin (maximal nodes of height
@@ -46,20 +57,24 @@ struct Schedule {
 struct Pass {
     int lin = 0, lout = 0;
     int t_tile = 0;
+    int S = 0;                   // positions per work item
+    int widest = 0;              // widest row window
     int max_lds_elems = 0;
+    bool fits = true;            // every program respects the kernel's prefetch limits
     std::vector<int32_t> hdrs;   // kHdrInts per program
     std::vector<int32_t> ops;    // 4 per op
     std::vector<int32_t> items;  // 4 per work item
 };
 
 struct AxisPlan {
-    int W = 0, H = 0, split = 0, S = 0;
+    int W = 0, H = 0, split = 0;
     std::vector<Pass> passes;
 };
 
-// Plans the passes for W lanes of H positions.  elem_bytes is the size of the
-// accumulator element (4 or 8).  Returns false and sets *err on failure.
-bool plan_axis(int W, int H, int split, int elem_bytes, const Schedule &sched,
+// Plans the passes for W lanes of H positions.  first_bytes and rest_bytes are
+// the LDS element sizes of the first pass and of the later passes.  Returns
+// false and sets *err on failure.
+bool plan_axis(int W, int H, int split, int first_bytes, int rest_bytes, const Schedule &sched,
                AxisPlan *out, std::string *err);
 
 }  // namespace fht

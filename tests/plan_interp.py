@@ -1,14 +1,23 @@
 """CPU interpreter of the library's tile programs (test helper, host logic only).
 
 It executes the planner's tables with the semantics the gfx950 kernel gives
-them (load / merge / store row operations, see ``plan.cpp``) and checks the
-invariants the kernel relies on: every LDS access is inside the program's
-footprint, no merge step reads a range another op of the same step writes,
-and every output element is written exactly once per pass.
+them and checks the invariants the kernel relies on:
+
+* entries cover whole 64-position chunks: load ``lds[d + c] = src[row][(s0 +
+  off + c) mod H]``, merge ``lds[d + c] = lds[a + c] + lds[b + c]`` for
+  ``c < 64 k``; store ``dst[row][s0 + c] = lds[d + c]`` for ``c < min(64 k,
+  limit)`` and ``s0 + c < H``;
+* every LDS access stays inside the program's footprint;
+* no merge step reads a range another entry of the same step writes;
+* every stored value was computed from loaded data only (positions a window
+  does not need may hold garbage, but none of it may reach an output);
+* every output element is written exactly once per pass.
 """
 import numpy as np
 
 import paper_2411_07351_amd as F
+
+CHUNK = 64
 
 
 def _overlap(r1, r2):
@@ -32,39 +41,49 @@ def run_plan_tables(plan_handle, img, q, check=True):
             hdr = tb["hdrs"][prog]
             first, nload, nstore, nsteps, lds_n, nops = (int(x) for x in hdr[:6])
             assert nops == nload + nstore + sum(int(c) for c in hdr[8:8 + nsteps])
+            assert int(hdr[25]) == tb["s_tile"]
             ops = tb["ops"][first:first + nops]
             lds = np.zeros(lds_n, dtype=src.dtype)
             valid = np.zeros(lds_n, dtype=bool)
-            for d, row, off, n in ops[:nload]:
+            if check and int(hdr[6]) == 0:
+                # first pass: one entry per lane of the root, in lane order
+                rows = ops[:nload, 1]
+                assert nload <= 64 and (np.diff(rows) == 1).all()
+                assert int(hdr[24]) == int((ops[:nload, 2] + CHUNK * ops[:nload, 3]).max())
+            for d, row, off, k in ops[:nload]:
+                n = CHUNK * int(k)
                 if check:
-                    assert 0 <= d and d + n <= lds_n and 0 <= row < W and off >= 0
+                    assert 1 <= k <= 4 and 0 <= d and d + n <= lds_n and 0 <= row < W and off >= 0
                 pos = (s0 + off + np.arange(n)) % H
                 lds[d:d + n] = src[row, pos]
                 valid[d:d + n] = True
-            k = nload
+            e = nload
             for step in range(nsteps):
                 cnt = int(hdr[8 + step])
-                step_ops = ops[k:k + cnt]
+                step_ops = ops[e:e + cnt]
                 if check:
-                    writes = [(d, d + n) for d, a, b, n in step_ops]
-                    reads = [(a, a + n) for d, a, b, n in step_ops] + \
-                            [(b, b + n) for d, a, b, n in step_ops]
+                    assert ((step_ops[:, 3] >= 1) & (step_ops[:, 3] <= 4)).all()
+                    writes = [(d, d + CHUNK * k) for d, a, b, k in step_ops]
+                    reads = [(a, a + CHUNK * k) for d, a, b, k in step_ops] + \
+                            [(b, b + CHUNK * k) for d, a, b, k in step_ops]
                     for w in writes:
                         assert w[0] >= 0 and w[1] <= lds_n
                         for r in reads:
                             assert r[0] >= 0 and r[1] <= lds_n
                             assert not _overlap(w, r), "merge step reads what it writes"
-                    for (d, a, b, n) in step_ops:
-                        assert valid[a:a + n].all() and valid[b:b + n].all(), "read before write"
-                new = [(d, lds[a:a + n] + lds[b:b + n]) for d, a, b, n in step_ops]
-                for (d, vals) in new:
+                new = []
+                for d, a, b, k in step_ops:
+                    n = CHUNK * int(k)
+                    new.append((d, lds[a:a + n] + lds[b:b + n], valid[a:a + n] & valid[b:b + n]))
+                for d, vals, ok in new:
                     lds[d:d + len(vals)] = vals
-                    valid[d:d + len(vals)] = True
-                k += cnt
-            for d, row, _, n in ops[k:k + nstore]:
-                m = min(int(n), H - int(s0))
+                    valid[d:d + len(vals)] = ok
+                e += cnt
+            for d, row, lim, k in ops[e:e + nstore]:
+                m = max(0, min(CHUNK * int(k), int(lim), H - int(s0)))
                 if check:
-                    assert valid[d:d + m].all()
+                    assert d + CHUNK * k <= lds_n
+                    assert valid[d:d + m].all(), "a stored value depends on unloaded data"
                 dst[row, s0:s0 + m] = lds[d:d + m]
                 written[row, s0:s0 + m] += 1
         if check:

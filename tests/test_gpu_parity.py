@@ -64,10 +64,11 @@ def test_shape_sweep_u8(F, split):
 
 
 @pytest.mark.parametrize("sched", [
-    dict(s_tile=16, first_levels=2, max_levels=2, lds_budget=4096, t_tile=0),
-    dict(s_tile=32, first_levels=3, max_levels=3, lds_budget=16384, t_tile=4),
-    dict(s_tile=256, first_levels=4, max_levels=5, lds_budget=65536, t_tile=16),
-    dict(s_tile=64, first_levels=1, max_levels=1, lds_budget=65536, t_tile=0),
+    dict(s_tile=64, s_tile_first=64, first_levels=2, max_levels=2, lds_budget=8192, t_tile=0),
+    dict(s_tile=128, s_tile_first=128, first_levels=3, max_levels=3, lds_budget=16384, t_tile=4),
+    dict(s_tile=192, s_tile_first=256, first_levels=4, max_levels=5, lds_budget=65536, t_tile=16),
+    dict(s_tile=64, s_tile_first=192, first_levels=1, max_levels=1, lds_budget=65536, t_tile=0),
+    dict(s_tile=256, s_tile_first=64, first_levels=6, max_levels=7, lds_budget=65536, t_tile=8),
 ])
 def test_schedules_u8(F, sched):
     rng = WL.rng_for(0, salt=8)

@@ -12,9 +12,10 @@ from plan_interp import run_plan_tables
 
 SCHEDULES = [
     None,
-    dict(s_tile=16, first_levels=2, max_levels=2, lds_budget=4096, t_tile=0),
-    dict(s_tile=32, first_levels=3, max_levels=3, lds_budget=16384, t_tile=4),
-    dict(s_tile=48, first_levels=1, max_levels=1, lds_budget=65536, t_tile=0),
+    dict(s_tile=64, s_tile_first=64, first_levels=2, max_levels=2, lds_budget=8192, t_tile=0),
+    dict(s_tile=128, s_tile_first=128, first_levels=3, max_levels=3, lds_budget=16384, t_tile=4),
+    dict(s_tile=64, s_tile_first=256, first_levels=1, max_levels=1, lds_budget=65536, t_tile=0),
+    dict(s_tile=256, s_tile_first=64, first_levels=6, max_levels=7, lds_budget=65536, t_tile=8),
 ]
 
 
@@ -85,4 +86,4 @@ def test_invalid_arguments():
     with pytest.raises(F.FhtError):
         F.fht_plan_create(4, 4, F.FHT_U8, 2, 15, None)
     with pytest.raises(F.FhtError):
-        F.fht_plan_create(4, 4, F.FHT_U8, 0, 15, F.fht_schedule(s_tile=17))
+        F.fht_plan_create(4, 4, F.FHT_U8, 0, 15, F.fht_schedule(s_tile=96))
