@@ -1,12 +1,14 @@
 #!/usr/bin/env python3
 """Throughput of the dyadic-pattern fast Hough transform on one MI355X.
 
-Workload (one "step"): a batch of 64 uint8 edge maps of 1021 x 1021
+Headline workload (one "step"): 64 uint8 edge maps of 1021 x 1021
 (Bernoulli(0.05) background plus 20 Bresenham segments, seed 2411_07351 + 2),
-all four quadrant Hough images with int32 accumulators, FHT2DS split.  The
-headline path launches each image separately (``fht_forward_launch`` for every
-fused pass); the same batch also runs batched (``fht_batch_run``: one launch
-per fused pass for all 64 images).  Inputs are resident in HBM before timing.
+all four quadrant Hough images with int32 outputs, FHT2DS split, launched per
+image (``fht_forward_launch`` for every fused pass of every image).  The same
+batch also runs batched (one launch per fused pass for all 64 images,
+replayed from a captured HIP graph), and a ragged batch of 512 edge maps with
+sides log-uniform in [32, 2048] runs both ways.  Inputs are resident in HBM
+before timing starts.
 
 Prints one JSON line.  ``--gpus`` above 1 is rejected: this build runs on one
 GPU (images would be sharded across GPUs with no exchange).
@@ -14,6 +16,7 @@ GPU (images would be sharded across GPUs with no exchange).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,6 +28,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, vendor figure
 METRIC = "input Mpixel/s + achieved HBM GB/s (batched vs plain); p50/p99 latency at fixed QPS"
+COMPULSORY_BPP = 17  # read a uint8 pixel once, write four int32 outputs once
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pass_kernels_1021x1021_u8.txt")
 
 
 def _parse():
@@ -36,24 +41,39 @@ def _parse():
     ap.add_argument("--rows", type=int, default=1021)
     ap.add_argument("--cols", type=int, default=1021)
     ap.add_argument("--split", default="S", choices=["S", "T"])
+    ap.add_argument("--ragged", type=int, default=512, help="images in the ragged batch (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU oracle sample budget (0 disables the cpu_baseline leg)")
-    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run a device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
-def _launch_bytes(plan, launch: int, in_bytes: int) -> int:
-    """Algorithmic HBM bytes of one launch of one image: compulsory reads + writes.
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "kernels.hpp", "plan.cpp", "plan.hpp"):
+        with open(os.path.join(ROOT, "paper_2411_07351_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
-    The first launch reads the image once and writes one accumulator per
-    output element of every quadrant; a later launch reads the previous pass's
-    accumulators and writes the next ones (4 bytes each).
-    """
-    elems = plan.out_elems
-    acc = 4
-    if launch == 0:
-        return plan.rows * plan.cols * in_bytes + elems * acc
-    return 2 * elems * acc
+
+def _traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    try:
+        vals = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                line = line.split("#", 1)[0].strip()
+                if "=" in line:
+                    k, v = (p.strip() for p in line.split("=", 1))
+                    vals[k] = v
+    except OSError:
+        return None
+    if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    v = vals.get(f"bytes_per_launch[{kernel}]")
+    return float(v) if v is not None else None
 
 
 def _cpu_baseline(imgs_np, split: int, budget_s: float):
@@ -66,10 +86,14 @@ def _cpu_baseline(imgs_np, split: int, budget_s: float):
             break
     dt = time.perf_counter() - t0
     R, C = imgs_np.shape[1:]
-    return {"value": done * R * C / dt / 1e6, "unit": "Mpixel/s", "cores": native.num_threads(),
-            "kind": "oracle",
-            "sample": f"{done} of {len(imgs_np)} images {R}x{C}, 4 quadrants, direct pattern sums "
-                      f"(C, OpenMP), {dt:.1f} s"}
+    return {"value": round(done * R * C / dt / 1e6, 3), "unit": "Mpixel/s",
+            "cores": native.num_threads(), "kind": "oracle",
+            "sample": f"{done} of {len(imgs_np)} images {R}x{C}, 4 quadrants, direct sums along "
+                      f"the generating patterns (C, OpenMP), {dt:.1f} s"}
+
+
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
 def main():
@@ -91,6 +115,8 @@ def main():
     torch.cuda.set_device(dev)
     split = 0 if args.split == "S" else 1
     n, R, C = args.images, args.rows, args.cols
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
 
     imgs_np = WL.edge_maps(WL.rng_for(2), n, R, C)
     imgs = torch.from_numpy(imgs_np).to(dev)
@@ -98,8 +124,7 @@ def main():
     outs = torch.empty((n, plan.out_elems), dtype=torch.int32, device=dev)
     ws = plan.new_ws(dev)
     nl = F.fht_plan_num_launches(plan.handle)
-    stream = torch.cuda.current_stream()
-    sh = stream.cuda_stream
+    info = [F.fht_plan_launch_info(plan.handle, l) for l in range(nl)]
     px_per_step = n * R * C
 
     def plain_step(events=None):
@@ -107,8 +132,7 @@ def main():
             ip, op = imgs[i].data_ptr(), outs[i].data_ptr()
             for l in range(nl):
                 if events is not None:
-                    events[l].append((torch.cuda.Event(enable_timing=True),
-                                      torch.cuda.Event(enable_timing=True)))
+                    events[l].append(_events(torch))
                     events[l][-1][0].record(stream)
                 F.fht_forward_launch(plan.handle, l, ip, op, ws.data_ptr(), sh)
                 if events is not None:
@@ -118,28 +142,35 @@ def main():
         plain_step()
     torch.cuda.synchronize()
 
-    # Timed region: K plain steps, every launch bracketed by HIP events on the
-    # stream it runs on.
-    events = [[] for _ in range(nl)]
+    # Timed region: K plain steps, bracketed by HIP events on the stream the
+    # kernels run on (and by the host clock around synchronisations).
+    a, b = _events(torch)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    a.record(stream)
+    for _ in range(args.steps):
+        plain_step()
+    b.record(stream)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    plain_event_ms = a.elapsed_time(b) / args.steps
+
+    # Kernel durations: the same K steps again with every launch bracketed by
+    # events (the events add launch gaps, so this loop is not the headline).
+    events = [[] for _ in range(nl)]
     for _ in range(args.steps):
         plain_step(events)
     torch.cuda.synchronize()
-    plain_s = time.perf_counter() - t0
-    launch_ms = [float(np.mean([a.elapsed_time(b) for a, b in ev])) for ev in events]
-    launch_total = [m * len(ev) for m, ev in zip(launch_ms, events)]
-    dom = int(np.argmax(launch_total))
-    dom_bytes = _launch_bytes(plan, dom, 1)
+    launch_ms = [float(np.mean([x.elapsed_time(y) for x, y in ev])) for ev in events]
+    totals = [m * len(ev) for m, ev in zip(launch_ms, events)]
+    dom = int(np.argmax(totals))
+    dom_bytes = info[dom]["bytes_in"] + info[dom]["bytes_out"]
     achieved = dom_bytes / (launch_ms[dom] * 1e-3) / 1e9
-
-    # Same steps without per-launch events (launch overhead of the events themselves).
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plain_step()
-    torch.cuda.synchronize()
-    plain_noev_s = time.perf_counter() - t0
+    kernels = ["fht_pass_kernel<256, unsigned char, unsigned short, unsigned short, true, false>",
+               "fht_pass_kernel<256, unsigned short, unsigned short, unsigned short, false, false>",
+               "fht_pass_kernel<256, unsigned short, int, int, false, false>"]
+    dom_kernel = kernels[dom] if nl == 3 and dom < 3 else f"launch {dom}"
+    traffic = _traffic(dom_kernel)
 
     value = px_per_step * args.steps / plain_s / 1e6
     result = {
@@ -157,58 +188,126 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{n} x {R}x{C} uint8 edge maps (Bernoulli 0.05 + 20 segments), "
-                        f"4 quadrants, FHT2D{args.split}, int32, plain per-image launches",
+                        f"4 quadrants, FHT2D{args.split}, int32 outputs, plain per-image launches",
             "images": n, "rows": R, "cols": C, "split": args.split, "path": "plain",
             "launches_per_image": nl,
         },
-        "effective_gbps": round(17 * px_per_step * args.steps / plain_s / 1e9, 1),
-        "plain_without_events_mpx_s": round(px_per_step * args.steps / plain_noev_s / 1e6, 1),
+        "effective_gbps": round(COMPULSORY_BPP * px_per_step * args.steps / plain_s / 1e9, 1),
+        "event_ms_per_step": round(plain_event_ms, 3),
         "roofline": {
             "bound": "hbm",
-            "kernel": f"launch {dom} of {nl} (fht_pass_kernel, "
-                      f"{'image' if dom == 0 else 'accumulator'} input)",
+            "kernel": dom_kernel,
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
-            "traffic": None,
+            "traffic": round(traffic, 0) if traffic is not None else None,
             "bytes_per_launch": dom_bytes,
             "avg_launch_us": round(launch_ms[dom] * 1e3, 2),
             "launch_avg_us": [round(m * 1e3, 2) for m in launch_ms],
+            "launch_bytes": [i["bytes_in"] + i["bytes_out"] for i in info],
+            "kernel_source_hash": kernel_source_hash(),
         },
     }
 
-    if not args.no_batched:
-        batch = F.Batch([plan] * n, [imgs[i] for i in range(n)], [outs[i] for i in range(n)])
-        bws = batch.new_ws(dev)
-        bl = batch.num_launches
+    # Batched: one launch per fused pass for all images, replayed from a graph.
+    batch = F.Batch([plan] * n, [imgs[i] for i in range(n)], [outs[i] for i in range(n)])
+    bws = batch.new_ws(dev)
+    graph = batch.capture(bws)
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    a, b = _events(torch)
+    a.record(stream)
+    for _ in range(args.steps):
+        graph.replay()
+    b.record(stream)
+    torch.cuda.synchronize()
+    bms = a.elapsed_time(b) / args.steps
+    per = [[] for _ in range(batch.num_launches)]
+    for _ in range(3):
+        for l in range(batch.num_launches):
+            e = _events(torch)
+            e[0].record(stream)
+            F.fht_batch_run_launch(batch.handle, l, bws.data_ptr(), sh)
+            e[1].record(stream)
+            per[l].append(e)
+    torch.cuda.synchronize()
+    per_ms = [float(np.median([x.elapsed_time(y) for x, y in ev])) for ev in per]
+    lbytes = [n * (i["bytes_in"] + i["bytes_out"]) for i in info]
+    result["batched"] = {
+        "value": round(px_per_step / (bms * 1e-3) / 1e6, 1),
+        "unit": "Mpixel/s",
+        "ms_per_step": round(bms, 4),
+        "graph": True,
+        "effective_gbps": round(COMPULSORY_BPP * px_per_step / (bms * 1e-3) / 1e9, 1),
+        "launch_ms": [round(m, 4) for m in per_ms],
+        "launch_gbps": ([round(by / (m * 1e-3) / 1e9, 1) for by, m in zip(lbytes, per_ms)]
+                        if len(per_ms) == len(lbytes) else None),
+        "path_gbps": round(sum(lbytes) / (bms * 1e-3) / 1e9, 1),
+        "path_frac": round(sum(lbytes) / (bms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+    }
+    del graph, batch, bws
+
+    if args.ragged > 0:
+        rng = WL.rng_for(3)
+        shapes = WL.ragged_shapes(rng, args.ragged, 32, 2048)
+        rimgs = [torch.from_numpy(WL.edge_map(rng, r, c)).to(dev) for r, c in shapes]
+        cache = {}
+        rplans = []
+        for r, c in shapes:
+            if (r, c) not in cache:
+                cache[(r, c)] = F.Plan(r, c, "u8", split)
+            rplans.append(cache[(r, c)])
+        routs = [p.new_out(dev) for p in rplans]
+        rpx = sum(r * c for r, c in shapes)
+        rb = F.Batch(rplans, rimgs, routs)
+        rws = rb.new_ws(dev)
+        rgraph = rb.capture(rws)
         for _ in range(args.warmup):
-            batch.run(bws)
+            rgraph.replay()
         torch.cuda.synchronize()
-        bev = [[] for _ in range(bl)]
-        t0 = time.perf_counter()
+        a, b = _events(torch)
+        a.record(stream)
         for _ in range(args.steps):
-            for l in range(bl):
-                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record(stream)
-                F.fht_batch_run_launch(batch.handle, l, bws.data_ptr(), sh)
-                b.record(stream)
-                bev[l].append((a, b))
+            rgraph.replay()
+        b.record(stream)
         torch.cuda.synchronize()
-        bs = time.perf_counter() - t0
-        bms = [float(np.mean([a.elapsed_time(b) for a, b in ev])) for ev in bev]
-        bbytes = [n * _launch_bytes(plan, l, 1) for l in range(bl)]
-        bgbps = [by / (m * 1e-3) / 1e9 for by, m in zip(bbytes, bms)]
-        result["batched"] = {
-            "value": round(px_per_step * args.steps / bs / 1e6, 1),
-            "unit": "Mpixel/s",
-            "ms_per_step": round(bs / args.steps * 1e3, 3),
-            "launch_avg_us": [round(m * 1e3, 2) for m in bms],
-            "launch_achieved_gbps": [round(g, 1) for g in bgbps],
-            "launch_frac": [round(g / HBM_PEAK_GBPS, 4) for g in bgbps],
-            "effective_gbps": round(17 * px_per_step * args.steps / bs / 1e9, 1),
+        rbms = a.elapsed_time(b) / args.steps
+        pws = torch.empty(max(p.ws_bytes for p in rplans) + 1, dtype=torch.uint8, device=dev)
+
+        def ragged_plain():
+            for p, im, o in zip(rplans, rimgs, routs):
+                F.fht_forward(p.handle, im.data_ptr(), o.data_ptr(), pws.data_ptr(), sh)
+
+        ragged_plain()
+        torch.cuda.synchronize()
+        psteps = max(1, args.steps // 3)
+        t0 = time.perf_counter()
+        for _ in range(psteps):
+            ragged_plain()
+        torch.cuda.synchronize()
+        rpms = (time.perf_counter() - t0) / psteps * 1e3
+        result["ragged"] = {
+            "workload": f"{args.ragged} uint8 edge maps, sides log-uniform in [32, 2048], "
+                        "4 quadrants, int32 outputs",
+            "mpixels": round(rpx / 1e6, 2),
+            "batched": {"value": round(rpx / (rbms * 1e-3) / 1e6, 1), "unit": "Mpixel/s",
+                        "ms_per_step": round(rbms, 3), "graph": True,
+                        "launches": rb.num_launches},
+            "plain": {"value": round(rpx / (rpms * 1e-3) / 1e6, 1), "unit": "Mpixel/s",
+                      "ms_per_step": round(rpms, 3)},
         }
-        del batch
+        del rgraph, rb, rws, routs, rimgs
+
+    if args.copy_mib > 0:
+        # A plain device copy of known size, for calibrating byte counters.
+        src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes"] = 2 * (args.copy_mib << 20)
 
     if args.cpu_seconds > 0:
         result["cpu_baseline"] = _cpu_baseline(imgs_np, split, args.cpu_seconds)

@@ -73,9 +73,11 @@ typedef struct fht_batch_s *fht_batch;
  *   first_levels  tree levels fused in the first pass (1..6)
  *   max_levels    tree levels fused in each later pass (1..16)
  *   lds_budget    LDS bytes a work item may use (1024..65536)
- *   t_tile        slope rows per work item in later passes (0 = choose)
+ *   t_tile        slope rows per work item in later passes, halved while the
+ *                 pass does not fit the LDS budget (-1: start from 32)
  *   s_tile_first  widest row window of the first pass (64..256, multiple of 64)
- *   threads       threads per workgroup: 256, 512 or 1024
+ *   threads       threads per workgroup of later passes: 256 or 512
+ *   threads_first threads per workgroup of the first pass: 256 or 512
  */
 typedef struct {
     int32_t s_tile;
@@ -85,6 +87,7 @@ typedef struct {
     int32_t t_tile;
     int32_t s_tile_first;
     int32_t threads;
+    int32_t threads_first;
 } fht_schedule;
 
 /* Human-readable name of a status code (static storage). */
@@ -115,6 +118,17 @@ size_t fht_plan_workspace_bytes(fht_plan plan);
 
 /* Number of kernel launches one fht_forward enqueues. */
 int32_t fht_plan_num_launches(fht_plan plan);
+
+/*
+ * Launch `launch` of fht_forward: its pass level, the algorithmic bytes it must
+ * move for one image (every element it reads once plus every element it
+ * writes once: the image or the previous pass's rows, then the next pass's rows
+ * or the output; uint8 images keep 16-bit rows while nodes are at most 257
+ * lanes wide) and its number of work items.  Any pointer may be NULL.
+ * Errors: FHT_EINVAL.
+ */
+fht_status fht_plan_launch_info(fht_plan plan, int32_t launch, int32_t *level,
+                                int64_t *bytes_in, int64_t *bytes_out, int32_t *n_items);
 
 /* Copy the plan's tables to the current HIP device (idempotent).  Needed only
  * before capturing fht_forward into a HIP graph.  Errors: FHT_ENODEV, FHT_ENOMEM,

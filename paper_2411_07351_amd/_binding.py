@@ -30,7 +30,7 @@ __all__ = [
     "LIB_PATH", "EXPORTED", "FhtError", "fht_schedule", "Plan", "Batch", "hough",
     "fht_status_string", "fht_plan_create", "fht_plan_destroy", "fht_plan_out_elems",
     "fht_plan_out_offset", "fht_plan_workspace_bytes", "fht_plan_num_launches",
-    "fht_plan_upload", "fht_forward", "fht_forward_launch", "fht_batch_create",
+    "fht_plan_launch_info", "fht_plan_upload", "fht_forward", "fht_forward_launch", "fht_batch_create",
     "fht_batch_workspace_bytes", "fht_batch_num_launches", "fht_batch_run",
     "fht_batch_run_launch", "fht_batch_destroy", "fht_plan_num_passes", "fht_plan_pass_tables",
 ]
@@ -46,7 +46,7 @@ STATUS = {0: "FHT_OK", -1: "FHT_EINVAL", -2: "FHT_EDTYPE", -3: "FHT_ENOMEM",
 EXPORTED = (
     "fht_status_string", "fht_plan_create", "fht_plan_destroy", "fht_plan_out_elems",
     "fht_plan_out_offset", "fht_plan_workspace_bytes", "fht_plan_num_launches",
-    "fht_plan_upload", "fht_forward", "fht_forward_launch", "fht_batch_create",
+    "fht_plan_launch_info", "fht_plan_upload", "fht_forward", "fht_forward_launch", "fht_batch_create",
     "fht_batch_workspace_bytes", "fht_batch_num_launches", "fht_batch_run",
     "fht_batch_run_launch", "fht_batch_destroy", "fht_plan_num_passes", "fht_plan_pass_tables",
 )
@@ -56,7 +56,7 @@ class fht_schedule(ctypes.Structure):
     _fields_ = [("s_tile", ctypes.c_int32), ("first_levels", ctypes.c_int32),
                 ("max_levels", ctypes.c_int32), ("lds_budget", ctypes.c_int32),
                 ("t_tile", ctypes.c_int32), ("s_tile_first", ctypes.c_int32),
-                ("threads", ctypes.c_int32)]
+                ("threads", ctypes.c_int32), ("threads_first", ctypes.c_int32)]
 
 
 _vp, _i32, _u32, _i64, _sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32,
@@ -80,6 +80,8 @@ _sig("fht_plan_out_elems", _sz, _vp)
 _sig("fht_plan_out_offset", _i64, _vp, _i32)
 _sig("fht_plan_workspace_bytes", _sz, _vp)
 _sig("fht_plan_num_launches", _i32, _vp)
+_sig("fht_plan_launch_info", _i32, _vp, _i32, _pi32, ctypes.POINTER(_i64),
+     ctypes.POINTER(_i64), _pi32)
 _sig("fht_plan_upload", _i32, _vp)
 _sig("fht_forward", _i32, _vp, _vp, _vp, _vp, _vp)
 _sig("fht_forward_launch", _i32, _vp, _i32, _vp, _vp, _vp, _vp)
@@ -139,6 +141,15 @@ def fht_plan_workspace_bytes(plan: int) -> int:
 
 def fht_plan_num_launches(plan: int) -> int:
     return _lib.fht_plan_num_launches(plan)
+
+
+def fht_plan_launch_info(plan: int, launch: int) -> dict:
+    level, n = _i32(), _i32()
+    bi, bo = _i64(), _i64()
+    _check(_lib.fht_plan_launch_info(plan, launch, ctypes.byref(level), ctypes.byref(bi),
+                                     ctypes.byref(bo), ctypes.byref(n)), "fht_plan_launch_info")
+    return {"level": level.value, "bytes_in": bi.value, "bytes_out": bo.value,
+            "n_items": n.value}
 
 
 def fht_plan_upload(plan: int) -> None:
@@ -334,6 +345,26 @@ class Batch:
             raise ValueError("workspace too small")
         fht_batch_run(self.handle, ws.data_ptr() if ws is not None else None,
                       _stream_handle(stream))
+
+    def capture(self, ws):
+        """Record the batch's launches into a HIP graph (``torch.cuda.CUDAGraph``).
+
+        ``graph.replay()`` then enqueues the whole batch at once.  The graph
+        holds raw pointers: keep this batch, its images, outputs and ``ws``
+        alive while it is used.
+        """
+        torch = _torch()
+        if self.ws_bytes and ws.numel() * ws.element_size() < self.ws_bytes:
+            raise ValueError("workspace too small")
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self.run(ws)  # warm-up outside the capture
+        torch.cuda.current_stream().wait_stream(side)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            self.run(ws)
+        return graph
 
 
 _plan_cache: dict = {}

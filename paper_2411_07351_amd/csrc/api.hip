@@ -2,16 +2,18 @@
 //
 // A plan holds, for the two lane orientations of an R x C image (lanes =
 // rows for quadrants V+/V-, lanes = columns for H+/H-), the fused-pass tile
-// programs made by the planner, concatenated into one header table, one op
-// table and one work-item list per launch.  Launch p runs pass p of every
-// selected quadrant that has one; pass 0 reads the image, the last pass of a
-// quadrant writes its output, and passes in between ping-pong through the
-// workspace.
+// programs made by the planner, concatenated into one header table and one
+// entry table, plus a list of launches.  Pass p of every selected quadrant
+// runs in the launches of level p (one per element-type combination: the two
+// orientations of a non-square image may differ); pass 0 reads the image, the
+// last pass of a quadrant writes its output, and passes in between ping-pong
+// through the workspace.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -23,11 +25,58 @@
 
 namespace {
 
+using fht::Combo;
 using fht::JobDesc;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Bytes of an output (and workspace) element.
 size_t acc_bytes(fht_dtype d) { return d == FHT_F64 ? 8 : 4; }
+
+fht_status hip_status(hipError_t e)
+{
+    if (e == hipSuccess) return FHT_OK;
+    if (e == hipErrorOutOfMemory) return FHT_ENOMEM;
+    if (e == hipErrorNoDevice || e == hipErrorInvalidDevice) return FHT_ENODEV;
+    return FHT_EHIP;
+}
+
+template <typename T>
+hipError_t upload(const std::vector<T> &host, T **dev)
+{
+    *dev = nullptr;
+    if (host.empty()) return hipSuccess;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(dev), host.size() * sizeof(T));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dev, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+// uint8 images keep 16-bit sums while nodes are at most this wide.
+constexpr int kNarrowWidth = 257;
+
+// Element types of pass p of an axis plan (see fht::Combo).
+Combo pass_combo(fht_dtype dt, const fht::AxisPlan &ax, size_t p)
+{
+    const bool final = p + 1 == ax.passes.size();
+    if (dt == FHT_F32) return p == 0 ? Combo::F32_FIRST : Combo::F32_LATER;
+    if (dt == FHT_F64) return p == 0 ? Combo::F64_FIRST : Combo::F64_LATER;
+    const bool narrow_out = ax.passes[p].max_root_w <= kNarrowWidth;
+    if (p == 0) return final ? Combo::U8_U16_I32 : Combo::U8_U16_U16;
+    const bool narrow_in = ax.passes[p - 1].max_root_w <= kNarrowWidth;
+    if (!narrow_in) return Combo::I32_I32_I32;
+    if (!narrow_out) return Combo::U16_I32_I32;
+    return final ? Combo::U16_U16_I32 : Combo::U16_U16_U16;
+}
+
+// One kernel launch: the work items of one level and one type combination.
+struct Launch {
+    int level = 0;
+    Combo combo = Combo::I32_I32_I32;
+    int lds_bytes = 0;
+    int threads = 256;
+    std::vector<int32_t> items;  // {program, job slot, first position, 0}
+    std::vector<int> jobs_q;     // plan launches: quadrant of each job slot
+};
 
 struct DevTables {
     int device = -1;
@@ -45,24 +94,6 @@ void free_tables(DevTables &t)
     t = DevTables{};
 }
 
-template <typename T>
-hipError_t upload(const std::vector<T> &host, T **dev)
-{
-    *dev = nullptr;
-    if (host.empty()) return hipSuccess;
-    hipError_t e = hipMalloc(reinterpret_cast<void **>(dev), host.size() * sizeof(T));
-    if (e != hipSuccess) return e;
-    return hipMemcpy(*dev, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice);
-}
-
-fht_status hip_status(hipError_t e)
-{
-    if (e == hipSuccess) return FHT_OK;
-    if (e == hipErrorOutOfMemory) return FHT_ENOMEM;
-    if (e == hipErrorNoDevice || e == hipErrorInvalidDevice) return FHT_ENODEV;
-    return FHT_EHIP;
-}
-
 }  // namespace
 
 struct fht_plan_s {
@@ -70,20 +101,16 @@ struct fht_plan_s {
     fht_dtype dtype = FHT_U8;
     fht_split split = FHT_SPLIT_S;
     uint32_t qmask = 0;
+    int threads = 512, threads_first = 256;
     fht::AxisPlan axis[2];
     int npass[4] = {0, 0, 0, 0};
     size_t out_off[4] = {0, 0, 0, 0};
     size_t out_elems = 0;
     size_t ws_off[4][2] = {};
     size_t ws_bytes = 0;
-    // Combined tables: programs of both views, all passes.
-    std::vector<int32_t> hdrs, ops;
-    std::vector<std::vector<int32_t>> items;  // per launch: {prog, job, s0, 0}
-    std::vector<std::vector<int>> jobs_q;     // per launch: quadrant of each job slot
-    std::vector<int> lds_bytes;               // per launch
-    int threads = 256;                        // per workgroup
-    // prog_base[v][p]: index of the first program of view v, pass p.
-    std::vector<int> prog_base[2];
+    std::vector<int32_t> hdrs, ops;  // programs of both views, all passes
+    std::vector<int> prog_base[2];   // first program of view v, pass p
+    std::vector<Launch> launches;    // in level order
     std::mutex mu;
     std::deque<DevTables> dev;  // stable addresses: launches hold pointers into it
 
@@ -96,8 +123,6 @@ struct fht_plan_s {
             (void)hipSetDevice(cur);
         }
     }
-
-    int view_of(int q) const { return q >> 1; }
 
     // Device tables for the current device, uploading them on first use.
     fht_status tables(const DevTables **out)
@@ -115,9 +140,9 @@ struct fht_plan_s {
         t.device = d;
         e = upload(hdrs, &t.hdrs);
         if (e == hipSuccess) e = upload(ops, &t.ops);
-        for (size_t p = 0; e == hipSuccess && p < items.size(); ++p) {
+        for (size_t l = 0; e == hipSuccess && l < launches.size(); ++l) {
             int32_t *ptr = nullptr;
-            e = upload(items[p], &ptr);
+            e = upload(launches[l].items, &ptr);
             t.items.push_back(ptr);
         }
         if (e != hipSuccess) {
@@ -128,6 +153,36 @@ struct fht_plan_s {
         *out = &dev.back();
         return FHT_OK;
     }
+
+    // The job of quadrant q in its pass `level`; workspace offsets are absolute
+    // (ws != null) or relative to the workspace (ws == null, batch tables).
+    JobDesc job(int q, int level, const void *img, void *out, char *ws, size_t ws_base) const
+    {
+        JobDesc jd;
+        std::memset(&jd, 0, sizeof(jd));
+        const fht::AxisPlan &ax = axis[q >> 1];
+        const bool final = level == npass[q] - 1;
+        int flags = ((q >> 1) ? fht::JF_COLS : 0) | ((q & 1) ? fht::JF_MIRROR : 0) |
+                    (final ? fht::JF_FINAL : 0);
+        if (level == 0) {
+            jd.src = img;
+        } else {
+            const size_t off = ws_base + ws_off[q][(level - 1) & 1];
+            jd.src = ws ? static_cast<const void *>(ws + off) : reinterpret_cast<const void *>(off);
+            if (!ws) flags |= fht::JF_SRC_WS;
+        }
+        if (final) {
+            jd.dst = static_cast<char *>(out) + out_off[q] * acc_bytes(dtype);
+        } else {
+            const size_t off = ws_base + ws_off[q][level & 1];
+            jd.dst = ws ? static_cast<void *>(ws + off) : reinterpret_cast<void *>(off);
+            if (!ws) flags |= fht::JF_DST_WS;
+        }
+        jd.H = ax.H;
+        jd.ld = C;
+        jd.flags = flags;
+        return jd;
+    }
 };
 
 struct fht_batch_s {
@@ -137,10 +192,8 @@ struct fht_batch_s {
     int32_t *hdrs = nullptr;
     int32_t *ops = nullptr;
     JobDesc *jobs = nullptr;
+    std::vector<Launch> launches;
     std::vector<int32_t *> items;
-    std::vector<int> n_items;
-    std::vector<int> lds_bytes;
-    int threads = 256;
 
     ~fht_batch_s()
     {
@@ -155,6 +208,76 @@ struct fht_batch_s {
         if (have) (void)hipSetDevice(cur);
     }
 };
+
+namespace {
+
+bool valid_threads(int t) { return t == 256 || t == 512; }
+
+fht_status make_schedule(const fht_schedule *sched, fht::Schedule *sc)
+{
+    if (sched) {
+        if (sched->s_tile) sc->s_tile = sched->s_tile;
+        if (sched->s_tile_first) sc->s_tile_first = sched->s_tile_first;
+        if (sched->threads) sc->threads = sched->threads;
+        if (sched->threads_first) sc->threads_first = sched->threads_first;
+        if (sched->first_levels) sc->first_levels = sched->first_levels;
+        if (sched->max_levels) sc->max_levels = sched->max_levels;
+        if (sched->lds_budget) sc->lds_budget = sched->lds_budget;
+        if (sched->t_tile) sc->t_tile = sched->t_tile < 0 ? 0 : sched->t_tile;
+    }
+    if (sc->s_tile < fht::kChunk || sc->s_tile > fht::kMaxTarget || sc->s_tile % fht::kChunk ||
+        sc->s_tile_first < fht::kChunk || sc->s_tile_first > fht::kMaxTarget ||
+        sc->s_tile_first % fht::kChunk || !valid_threads(sc->threads) ||
+        !valid_threads(sc->threads_first) || sc->first_levels < 1 ||
+        sc->first_levels > fht::kMaxFirstLevels || sc->max_levels < 1 ||
+        sc->max_levels > fht::kMaxSteps || sc->lds_budget < 1024 || sc->lds_budget > 65536 ||
+        sc->t_tile < 0 || sc->t_tile > 4096)
+        return FHT_EINVAL;
+    return FHT_OK;
+}
+
+fht_status forward_one(fht_plan plan, const DevTables *t, size_t l, const void *d_img,
+                       void *d_out, void *d_ws, void *stream)
+{
+    const Launch &L = plan->launches[l];
+    fht::PassArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.items = reinterpret_cast<const int4 *>(t->items[l]);
+    a.hdrs = t->hdrs;
+    a.ops = reinterpret_cast<const int4 *>(t->ops);
+    for (size_t j = 0; j < L.jobs_q.size(); ++j)
+        a.inl[j] = plan->job(L.jobs_q[j], L.level, d_img, d_out, static_cast<char *>(d_ws), 0);
+    const int nitems = static_cast<int>(L.items.size() / 4);
+    return hip_status(fht::launch_pass(L.combo, a, nitems, L.lds_bytes, L.threads,
+                                       static_cast<hipStream_t>(stream)));
+}
+
+fht_status forward_checks(fht_plan plan, const void *d_img, void *d_out, void *d_ws,
+                          const DevTables **t)
+{
+    if (!plan || !d_img || !d_out) return FHT_EINVAL;
+    if (plan->ws_bytes && !d_ws) return FHT_EINVAL;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0) return FHT_ENODEV;
+    return plan->tables(t);
+}
+
+fht_status batch_one(fht_batch batch, size_t l, void *d_ws, void *stream)
+{
+    const Launch &L = batch->launches[l];
+    fht::PassArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.items = reinterpret_cast<const int4 *>(batch->items[l]);
+    a.hdrs = batch->hdrs;
+    a.ops = reinterpret_cast<const int4 *>(batch->ops);
+    a.jobs = batch->jobs;
+    a.ws = static_cast<char *>(d_ws);
+    const int nitems = static_cast<int>(L.items.size() / 4);
+    return hip_status(fht::launch_pass(L.combo, a, nitems, L.lds_bytes, L.threads,
+                                       static_cast<hipStream_t>(stream)));
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -181,24 +304,8 @@ fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, fht_dtype 
     if (quadrant_mask == 0 || quadrant_mask > 15) return FHT_EINVAL;
     if (split != FHT_SPLIT_S && split != FHT_SPLIT_T) return FHT_EINVAL;
     if (dtype != FHT_U8 && dtype != FHT_F32 && dtype != FHT_F64) return FHT_EDTYPE;
-
     fht::Schedule sc;
-    if (sched) {
-        if (sched->s_tile) sc.s_tile = sched->s_tile;
-        if (sched->s_tile_first) sc.s_tile_first = sched->s_tile_first;
-        if (sched->threads) sc.threads = sched->threads;
-        if (sched->first_levels) sc.first_levels = sched->first_levels;
-        if (sched->max_levels) sc.max_levels = sched->max_levels;
-        if (sched->lds_budget) sc.lds_budget = sched->lds_budget;
-        if (sched->t_tile) sc.t_tile = sched->t_tile;
-    }
-    if (sc.s_tile < fht::kChunk || sc.s_tile > fht::kMaxTarget || sc.s_tile % fht::kChunk ||
-        sc.s_tile_first < fht::kChunk || sc.s_tile_first > fht::kMaxTarget ||
-        sc.s_tile_first % fht::kChunk || sc.first_levels < 1 ||
-        (sc.threads != 256 && sc.threads != 512 && sc.threads != 1024) ||
-        sc.first_levels > fht::kMaxFirstLevels || sc.max_levels < 1 || sc.max_levels > fht::kMaxSteps ||
-        sc.lds_budget < 1024 || sc.lds_budget > 65536 || sc.t_tile < 0 || sc.t_tile > 4096)
-        return FHT_EINVAL;
+    if (make_schedule(sched, &sc) != FHT_OK) return FHT_EINVAL;
 
     fht_plan_s *p = new (std::nothrow) fht_plan_s;
     if (!p) return FHT_ENOMEM;
@@ -209,23 +316,25 @@ fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, fht_dtype 
         p->split = split;
         p->qmask = quadrant_mask;
         p->threads = sc.threads;
+        p->threads_first = sc.threads_first;
         const int eb = static_cast<int>(acc_bytes(dtype));
-        // uint8 images: first-pass sums of at most 64 lanes fit 16 bits in LDS.
-        const int first_eb = dtype == FHT_U8 ? 2 : eb;
+        fht::ElemRule rule;
+        rule.narrow_bytes = dtype == FHT_U8 ? 2 : eb;
+        rule.wide_bytes = eb;
+        rule.narrow_width = dtype == FHT_U8 ? kNarrowWidth : 0;
         for (int v = 0; v < 2; ++v) {
-            const bool used = quadrant_mask & (3u << (2 * v));
-            if (!used) continue;
+            if (!(quadrant_mask & (3u << (2 * v)))) continue;
             const int W = v == 0 ? rows : cols, H = v == 0 ? cols : rows;
             std::string err;
-            if (!fht::plan_axis(W, H, static_cast<int>(split), first_eb, eb, sc, &p->axis[v],
-                                &err)) {
+            if (!fht::plan_axis(W, H, static_cast<int>(split), rule, sc, &p->axis[v], &err)) {
                 delete p;
                 return FHT_EINVAL;
             }
         }
-        // Output and workspace layout.
+        // Output and workspace layout (workspace rows are sized for the widest
+        // element type any pass stores).
         size_t off = 0, ws = 0;
-        int nlaunch = 0;
+        int nlevels = 0;
         for (int q = 0; q < 4; ++q) {
             if (!(quadrant_mask & (1u << q))) continue;
             const fht::AxisPlan &ax = p->axis[q >> 1];
@@ -233,7 +342,7 @@ fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, fht_dtype 
             p->out_off[q] = off;
             off += wh;
             p->npass[q] = static_cast<int>(ax.passes.size());
-            nlaunch = std::max(nlaunch, p->npass[q]);
+            nlevels = std::max(nlevels, p->npass[q]);
             const int nbuf = std::min(p->npass[q] - 1, 2);
             for (int b = 0; b < nbuf; ++b) {
                 p->ws_off[q][b] = ws;
@@ -255,25 +364,35 @@ fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, fht_dtype 
                 p->ops.insert(p->ops.end(), ps.ops.begin(), ps.ops.end());
             }
         }
-        // Per-launch work lists: job slot j of launch l is the j-th selected
-        // quadrant that still has a pass l.
-        p->items.resize(nlaunch);
-        p->jobs_q.resize(nlaunch);
-        p->lds_bytes.assign(nlaunch, 0);
-        for (int l = 0; l < nlaunch; ++l) {
+        // Launches: level by level, one per type combination; job slot j of a
+        // launch is its j-th quadrant.
+        for (int l = 0; l < nlevels; ++l) {
+            std::vector<size_t> level_launches;
             for (int q = 0; q < 4; ++q) {
                 if (!(quadrant_mask & (1u << q)) || p->npass[q] <= l) continue;
                 const int v = q >> 1;
-                const int job = static_cast<int>(p->jobs_q[l].size());
-                p->jobs_q[l].push_back(q);
                 const fht::Pass &ps = p->axis[v].passes[l];
-                for (size_t i = 0; i < ps.items.size(); i += 4) {
-                    p->items[l].push_back(ps.items[i] + p->prog_base[v][l]);
-                    p->items[l].push_back(job);
-                    p->items[l].push_back(ps.items[i + 2]);
-                    p->items[l].push_back(0);
+                const Combo combo = pass_combo(dtype, p->axis[v], l);
+                Launch *L = nullptr;
+                for (size_t k : level_launches)
+                    if (p->launches[k].combo == combo) L = &p->launches[k];
+                if (!L) {
+                    level_launches.push_back(p->launches.size());
+                    p->launches.emplace_back();
+                    L = &p->launches.back();
+                    L->level = l;
+                    L->combo = combo;
+                    L->threads = l == 0 ? sc.threads_first : sc.threads;
                 }
-                p->lds_bytes[l] = std::max(p->lds_bytes[l], ps.max_lds_elems * (l == 0 ? first_eb : eb));
+                const int job = static_cast<int>(L->jobs_q.size());
+                L->jobs_q.push_back(q);
+                for (size_t i = 0; i < ps.items.size(); i += 4) {
+                    L->items.push_back(ps.items[i] + p->prog_base[v][l]);
+                    L->items.push_back(job);
+                    L->items.push_back(ps.items[i + 2]);
+                    L->items.push_back(0);
+                }
+                L->lds_bytes = std::max(L->lds_bytes, ps.max_lds_elems * ps.elem_bytes);
             }
         }
     } catch (const std::bad_alloc &) {
@@ -298,7 +417,45 @@ size_t fht_plan_workspace_bytes(fht_plan plan) { return plan ? plan->ws_bytes : 
 
 int32_t fht_plan_num_launches(fht_plan plan)
 {
-    return plan ? static_cast<int32_t>(plan->items.size()) : 0;
+    return plan ? static_cast<int32_t>(plan->launches.size()) : 0;
+}
+
+fht_status fht_plan_launch_info(fht_plan plan, int32_t launch, int32_t *level,
+                                int64_t *bytes_in, int64_t *bytes_out, int32_t *n_items)
+{
+    if (!plan || launch < 0 || launch >= static_cast<int32_t>(plan->launches.size()))
+        return FHT_EINVAL;
+    const Launch &L = plan->launches[launch];
+    int in_b = 4, out_b = 4;
+    switch (L.combo) {
+    case Combo::U8_U16_U16: in_b = 1; out_b = 2; break;
+    case Combo::U8_U16_I32: in_b = 1; out_b = 4; break;
+    case Combo::U16_U16_U16: in_b = 2; out_b = 2; break;
+    case Combo::U16_U16_I32: in_b = 2; out_b = 4; break;
+    case Combo::U16_I32_I32: in_b = 2; out_b = 4; break;
+    case Combo::I32_I32_I32: in_b = 4; out_b = 4; break;
+    case Combo::F32_FIRST: case Combo::F32_LATER: in_b = 4; out_b = 4; break;
+    case Combo::F64_FIRST: case Combo::F64_LATER: in_b = 8; out_b = 8; break;
+    }
+    int64_t bin = 0, bout = 0;
+    bool image_counted = false;
+    for (int q : L.jobs_q) {
+        const fht::AxisPlan &ax = plan->axis[q >> 1];
+        const int64_t wh = static_cast<int64_t>(ax.W) * ax.H;
+        if (L.level == 0) {
+            // every quadrant of a launch reads the same image; count it once
+            if (!image_counted) bin += static_cast<int64_t>(plan->R) * plan->C * in_b;
+            image_counted = true;
+        } else {
+            bin += wh * in_b;
+        }
+        bout += wh * out_b;
+    }
+    if (level) *level = L.level;
+    if (bytes_in) *bytes_in = bin;
+    if (bytes_out) *bytes_out = bout;
+    if (n_items) *n_items = static_cast<int32_t>(L.items.size() / 4);
+    return FHT_OK;
 }
 
 fht_status fht_plan_upload(fht_plan plan)
@@ -310,53 +467,11 @@ fht_status fht_plan_upload(fht_plan plan)
     return plan->tables(&t);
 }
 
-static fht_status forward_one(fht_plan plan, const DevTables *t, size_t l, const void *d_img,
-                              void *d_out, void *d_ws, void *stream)
-{
-    const size_t eb = acc_bytes(plan->dtype);
-    const fht::Dt dt = static_cast<fht::Dt>(plan->dtype);
-    char *ws = static_cast<char *>(d_ws);
-    char *out = static_cast<char *>(d_out);
-    fht::PassArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.items = reinterpret_cast<const int4 *>(t->items[l]);
-    a.hdrs = t->hdrs;
-    a.ops = reinterpret_cast<const int4 *>(t->ops);
-    a.jobs = nullptr;
-    a.ws = nullptr;
-    for (size_t j = 0; j < plan->jobs_q[l].size(); ++j) {
-        const int q = plan->jobs_q[l][j];
-        const fht::AxisPlan &ax = plan->axis[q >> 1];
-        const bool final = static_cast<int>(l) == plan->npass[q] - 1;
-        JobDesc &jd = a.inl[j];
-        jd.src = (l == 0) ? d_img : ws + plan->ws_off[q][(l - 1) & 1];
-        jd.dst = final ? out + plan->out_off[q] * eb : ws + plan->ws_off[q][l & 1];
-        jd.H = ax.H;
-        jd.ld = plan->C;
-        jd.flags = ((q >> 1) ? fht::JF_COLS : 0) | ((q & 1) ? fht::JF_MIRROR : 0) |
-                   (final ? fht::JF_FINAL : 0);
-    }
-    const int nitems = static_cast<int>(plan->items[l].size() / 4);
-    const hipError_t e = fht::launch_pass(dt, l == 0, a, nitems, plan->lds_bytes[l],
-                                          plan->threads, static_cast<hipStream_t>(stream));
-    return hip_status(e);
-}
-
-static fht_status forward_checks(fht_plan plan, const void *d_img, void *d_out, void *d_ws,
-                                 const DevTables **t)
-{
-    if (!plan || !d_img || !d_out) return FHT_EINVAL;
-    if (plan->ws_bytes && !d_ws) return FHT_EINVAL;
-    int n = 0;
-    if (hipGetDeviceCount(&n) != hipSuccess || n == 0) return FHT_ENODEV;
-    return plan->tables(t);
-}
-
 fht_status fht_forward(fht_plan plan, const void *d_img, void *d_out, void *d_ws, void *stream)
 {
     const DevTables *t = nullptr;
     fht_status st = forward_checks(plan, d_img, d_out, d_ws, &t);
-    for (size_t l = 0; st == FHT_OK && l < plan->items.size(); ++l)
+    for (size_t l = 0; st == FHT_OK && l < plan->launches.size(); ++l)
         st = forward_one(plan, t, l, d_img, d_out, d_ws, stream);
     return st;
 }
@@ -367,7 +482,7 @@ fht_status fht_forward_launch(fht_plan plan, int32_t launch, const void *d_img, 
     const DevTables *t = nullptr;
     fht_status st = forward_checks(plan, d_img, d_out, d_ws, &t);
     if (st != FHT_OK) return st;
-    if (launch < 0 || launch >= static_cast<int32_t>(plan->items.size())) return FHT_EINVAL;
+    if (launch < 0 || launch >= static_cast<int32_t>(plan->launches.size())) return FHT_EINVAL;
     return forward_one(plan, t, static_cast<size_t>(launch), d_img, d_out, d_ws, stream);
 }
 
@@ -383,15 +498,15 @@ fht_status fht_batch_create(fht_batch *out, const fht_plan *plans, int32_t n,
         if (plans[i]->dtype != plans[0]->dtype || plans[i]->split != plans[0]->split)
             return FHT_EDTYPE;
     for (int i = 1; i < n; ++i)
-        if (plans[i]->threads != plans[0]->threads) return FHT_EINVAL;
+        if (plans[i]->threads != plans[0]->threads ||
+            plans[i]->threads_first != plans[0]->threads_first)
+            return FHT_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return FHT_ENODEV;
 
     fht_batch_s *b = new (std::nothrow) fht_batch_s;
     if (!b) return FHT_ENOMEM;
     b->dtype = plans[0]->dtype;
-    b->threads = plans[0]->threads;
-    const size_t eb = acc_bytes(b->dtype);
     hipError_t e = hipGetDevice(&b->device);
     if (e != hipSuccess) {
         delete b;
@@ -400,81 +515,65 @@ fht_status fht_batch_create(fht_batch *out, const fht_plan *plans, int32_t n,
     try {
         // Distinct plans share one copy of their tables.
         std::vector<fht_plan> uniq;
-        std::vector<int> hdr_base, op_base;
+        std::vector<int> hdr_base;
         std::vector<int32_t> hdrs, ops;
         auto table_of = [&](fht_plan p) {
             for (size_t u = 0; u < uniq.size(); ++u)
                 if (uniq[u] == p) return static_cast<int>(u);
             uniq.push_back(p);
             hdr_base.push_back(static_cast<int>(hdrs.size() / fht::kHdrInts));
-            op_base.push_back(static_cast<int>(ops.size() / 4));
+            const int op_base = static_cast<int>(ops.size() / 4);
             for (size_t i = 0; i < p->hdrs.size(); i += fht::kHdrInts) {
                 hdrs.insert(hdrs.end(), p->hdrs.begin() + i, p->hdrs.begin() + i + fht::kHdrInts);
-                hdrs[hdrs.size() - fht::kHdrInts] += op_base.back();
+                hdrs[hdrs.size() - fht::kHdrInts] += op_base;
             }
             ops.insert(ops.end(), p->ops.begin(), p->ops.end());
             return static_cast<int>(uniq.size() - 1);
         };
-        size_t nlaunch = 0;
-        for (int i = 0; i < n; ++i) nlaunch = std::max(nlaunch, plans[i]->items.size());
-        std::vector<std::vector<int32_t>> items(nlaunch);
+        // Batch launches keyed by (level, combination), in level order.
+        std::map<std::pair<int, int>, size_t> key;
         std::vector<JobDesc> jobs;
-        b->lds_bytes.assign(nlaunch, 0);
         size_t ws = 0;
         for (int i = 0; i < n; ++i) {
             const fht_plan p = plans[i];
             const int u = table_of(p);
             const size_t ws_base = ws;
             ws += align_up(p->ws_bytes, 256);
-            for (size_t l = 0; l < p->items.size(); ++l) {
+            for (const Launch &L : p->launches) {
+                const auto k = std::make_pair(L.level, static_cast<int>(L.combo));
+                auto found = key.find(k);
+                if (found == key.end()) {
+                    found = key.emplace(k, b->launches.size()).first;
+                    b->launches.emplace_back();
+                    b->launches.back().level = L.level;
+                    b->launches.back().combo = L.combo;
+                    b->launches.back().threads = L.threads;
+                }
+                Launch &B = b->launches[found->second];
                 std::vector<int> slot;
-                for (size_t j = 0; j < p->jobs_q[l].size(); ++j) {
-                    const int q = p->jobs_q[l][j];
-                    const fht::AxisPlan &ax = p->axis[q >> 1];
-                    const bool final = static_cast<int>(l) == p->npass[q] - 1;
-                    JobDesc jd;
-                    std::memset(&jd, 0, sizeof(jd));
-                    int flags = ((q >> 1) ? fht::JF_COLS : 0) | ((q & 1) ? fht::JF_MIRROR : 0) |
-                                (final ? fht::JF_FINAL : 0);
-                    if (l == 0) {
-                        jd.src = d_imgs[i];
-                    } else {
-                        jd.src = reinterpret_cast<const void *>(ws_base + p->ws_off[q][(l - 1) & 1]);
-                        flags |= fht::JF_SRC_WS;
-                    }
-                    if (final) {
-                        jd.dst = static_cast<char *>(d_outs[i]) + p->out_off[q] * eb;
-                    } else {
-                        jd.dst = reinterpret_cast<void *>(ws_base + p->ws_off[q][l & 1]);
-                        flags |= fht::JF_DST_WS;
-                    }
-                    jd.H = ax.H;
-                    jd.ld = p->C;
-                    jd.flags = flags;
+                for (int q : L.jobs_q) {
                     slot.push_back(static_cast<int>(jobs.size()));
-                    jobs.push_back(jd);
+                    jobs.push_back(p->job(q, L.level, d_imgs[i], d_outs[i], nullptr, ws_base));
                 }
-                const std::vector<int32_t> &src = p->items[l];
-                for (size_t k = 0; k < src.size(); k += 4) {
-                    const int prog = src[k];
-                    // rebase the program index from the plan's table to the batch's
-                    items[l].push_back(prog + hdr_base[u]);
-                    items[l].push_back(slot[src[k + 1]]);
-                    items[l].push_back(src[k + 2]);
-                    items[l].push_back(0);
+                for (size_t k4 = 0; k4 < L.items.size(); k4 += 4) {
+                    B.items.push_back(L.items[k4] + hdr_base[u]);
+                    B.items.push_back(slot[L.items[k4 + 1]]);
+                    B.items.push_back(L.items[k4 + 2]);
+                    B.items.push_back(0);
                 }
-                b->lds_bytes[l] = std::max(b->lds_bytes[l], p->lds_bytes[l]);
+                B.lds_bytes = std::max(B.lds_bytes, L.lds_bytes);
             }
         }
+        std::stable_sort(b->launches.begin(), b->launches.end(),
+                         [](const Launch &x, const Launch &y) { return x.level < y.level; });
         b->ws_bytes = ws;
         e = upload(hdrs, &b->hdrs);
         if (e == hipSuccess) e = upload(ops, &b->ops);
         if (e == hipSuccess) e = upload(jobs, &b->jobs);
-        for (size_t l = 0; e == hipSuccess && l < nlaunch; ++l) {
+        for (size_t l = 0; e == hipSuccess && l < b->launches.size(); ++l) {
             int32_t *ptr = nullptr;
-            e = upload(items[l], &ptr);
+            e = upload(b->launches[l].items, &ptr);
             b->items.push_back(ptr);
-            b->n_items.push_back(static_cast<int>(items[l].size() / 4));
         }
         if (e != hipSuccess) {
             delete b;
@@ -492,22 +591,7 @@ size_t fht_batch_workspace_bytes(fht_batch batch) { return batch ? batch->ws_byt
 
 int32_t fht_batch_num_launches(fht_batch batch)
 {
-    return batch ? static_cast<int32_t>(batch->items.size()) : 0;
-}
-
-static fht_status batch_one(fht_batch batch, size_t l, void *d_ws, void *stream)
-{
-    fht::PassArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.items = reinterpret_cast<const int4 *>(batch->items[l]);
-    a.hdrs = batch->hdrs;
-    a.ops = reinterpret_cast<const int4 *>(batch->ops);
-    a.jobs = batch->jobs;
-    a.ws = static_cast<char *>(d_ws);
-    const hipError_t e = fht::launch_pass(static_cast<fht::Dt>(batch->dtype), l == 0, a,
-                                          batch->n_items[l], batch->lds_bytes[l], batch->threads,
-                                          static_cast<hipStream_t>(stream));
-    return hip_status(e);
+    return batch ? static_cast<int32_t>(batch->launches.size()) : 0;
 }
 
 fht_status fht_batch_run(fht_batch batch, void *d_ws, void *stream)
@@ -515,7 +599,7 @@ fht_status fht_batch_run(fht_batch batch, void *d_ws, void *stream)
     if (!batch) return FHT_EINVAL;
     if (batch->ws_bytes && !d_ws) return FHT_EINVAL;
     fht_status st = FHT_OK;
-    for (size_t l = 0; st == FHT_OK && l < batch->items.size(); ++l)
+    for (size_t l = 0; st == FHT_OK && l < batch->launches.size(); ++l)
         st = batch_one(batch, l, d_ws, stream);
     return st;
 }
@@ -524,7 +608,7 @@ fht_status fht_batch_run_launch(fht_batch batch, int32_t launch, void *d_ws, voi
 {
     if (!batch) return FHT_EINVAL;
     if (batch->ws_bytes && !d_ws) return FHT_EINVAL;
-    if (launch < 0 || launch >= static_cast<int32_t>(batch->items.size())) return FHT_EINVAL;
+    if (launch < 0 || launch >= static_cast<int32_t>(batch->launches.size())) return FHT_EINVAL;
     return batch_one(batch, static_cast<size_t>(launch), d_ws, stream);
 }
 

@@ -1,7 +1,7 @@
 // gfx950 kernels of the dyadic-pattern fast Hough transform.
 //
 // One launch executes one fused pass of Alg. 1 for many work items.  A work
-// item (one workgroup of 4, 8 or 16 wavefronts) runs a planner-made program:
+// item (one workgroup of 4 or 8 wavefronts) runs a planner-made program:
 // it loads the rows its slope tile needs into LDS, runs the merge steps of
 // Alg. 1 (row t of a node = row t0 of the left child + row t1 of the right
 // child rotated by t - t1) entirely in LDS, and writes its output rows back.
@@ -124,28 +124,55 @@ __device__ __forceinline__ void merge_group(TL *lds, const int4 &mine, int m, in
 }
 
 // Later-pass loads {dst, row, offset, K}: lds[dst + c] = src[row][(s0 + offset + c) mod H].
-// 32-bit elements go straight from HBM to LDS; float64 goes through registers.
-template <int K, int NW, typename TL>
-__device__ __forceinline__ void load_rows(TL *lds, const int4 *ent, int n, const TL *src, int H,
+// Rows go straight from HBM into 32-bit LDS elements when the LDS type is
+// 32-bit (global_load_lds_dword; the 16-bit form zero-extends each lane's
+// value into its dword, which widens 16-bit rows on the way); other rows go
+// through registers, four rows of loads in flight before their LDS writes.
+template <int K, int NW, typename TS, typename TL>
+__device__ __forceinline__ void load_rows(TL *lds, const int4 *ent, int n, const TS *src, int H,
                                           int s0, int wave, int lane)
 {
     for (int g = wave; g < n; g += 64 * NW) {
         const int4 mine = fetch_desc<NW>(ent, n, g, lane);
         const int m = group_size<NW>(n, g);
-        for (int j = 0; j < m; ++j) {
-            int base = s0 + rl(mine.z, j);
-            if (base >= H) base %= H;
-            const TL *rowp = src + static_cast<size_t>(rl(mine.y, j)) * H;
-            TL *dst = lds + rl(mine.x, j);
+        if constexpr (sizeof(TL) == 4 && (sizeof(TS) == 4 || sizeof(TS) == 2)) {
+            for (int j = 0; j < m; ++j) {
+                int base = s0 + rl(mine.z, j);
+                if (base >= H) base %= H;
+                const TS *rowp = src + static_cast<size_t>(rl(mine.y, j)) * H;
+                TL *dst = lds + rl(mine.x, j);
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const TL *gp = rowp + wrap(base + 64 * k + lane, H);
-                if constexpr (sizeof(TL) == 4) {
-                    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(gp),
-                                                     (__attribute__((address_space(3))) void *)(dst + 64 * k),
-                                                     4, 0, 0);
-                } else {
-                    dst[64 * k + lane] = *gp;
+                for (int k = 0; k < K; ++k) {
+                    const TS *gp = rowp + wrap(base + 64 * k + lane, H);
+                    auto *g1 = (const __attribute__((address_space(1))) void *)(gp);
+                    auto *l3 = (__attribute__((address_space(3))) void *)(dst + 64 * k);
+                    if constexpr (sizeof(TS) == 2)
+                        __builtin_amdgcn_global_load_lds(g1, l3, 2, 0, 0);
+                    else
+                        __builtin_amdgcn_global_load_lds(g1, l3, 4, 0, 0);
+                }
+            }
+        } else {
+            constexpr int R = 4;
+            for (int j0 = 0; j0 < m; j0 += R) {
+                TL v[R][K];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int j = min(j0 + r, m - 1);
+                    int base = s0 + rl(mine.z, j);
+                    if (base >= H) base %= H;
+                    const TS *rowp = src + static_cast<size_t>(rl(mine.y, j)) * H;
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+                        v[r][k] = static_cast<TL>(rowp[wrap(base + 64 * k + lane, H)]);
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (j0 + r < m) {
+                        TL *dst = lds + rl(mine.x, j0 + r) + lane;
+#pragma unroll
+                        for (int k = 0; k < K; ++k) dst[64 * k] = v[r][k];
+                    }
                 }
             }
         }
@@ -218,8 +245,8 @@ __device__ __forceinline__ void load_image(TL *lds, const int4 *ent, int nl, int
 // Stores {src, row, limit, K}: dst[row][s0 + c] = lds[src + c] for c < limit
 // and s0 + c < H; the final output of a negative-slope quadrant is written
 // back in un-mirrored position order.
-template <int K, int NW, typename TL, typename TAcc>
-__device__ __forceinline__ void store_rows(const TL *lds, const int4 *ent, int n, TAcc *dst, int H,
+template <int K, int NW, typename TL, typename TD>
+__device__ __forceinline__ void store_rows(const TL *lds, const int4 *ent, int n, TD *dst, int H,
                                            int s0, bool unmirror, int wave, int lane)
 {
     for (int g = wave; g < n; g += 64 * NW) {
@@ -228,7 +255,7 @@ __device__ __forceinline__ void store_rows(const TL *lds, const int4 *ent, int n
         for (int j = 0; j < m; ++j) {
             const int lim = min(rl(mine.z, j), H - s0);
             const TL *srcp = lds + rl(mine.x, j) + lane;
-            TAcc *rowp = dst + static_cast<size_t>(rl(mine.y, j)) * H;
+            TD *rowp = dst + static_cast<size_t>(rl(mine.y, j)) * H;
             TL v[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) v[k] = srcp[64 * k];
@@ -237,14 +264,14 @@ __device__ __forceinline__ void store_rows(const TL *lds, const int4 *ent, int n
                 const int c = 64 * k + lane;
                 if (c < lim) {
                     const int s = s0 + c;
-                    rowp[(unmirror && s != 0) ? H - s : s] = static_cast<TAcc>(v[k]);
+                    rowp[(unmirror && s != 0) ? H - s : s] = static_cast<TD>(v[k]);
                 }
             }
         }
     }
 }
 
-template <int NT, int K, typename TSrc, typename TL, typename TAcc, bool FROM_IMAGE>
+template <int NT, int K, typename TSrc, typename TL, typename TD, bool FROM_IMAGE>
 __device__ __forceinline__ void run_item(TL *lds, cptr<int32_t> hdr, const int4 *ent,
                                          const JobDesc &job, const char *src, char *dst, int s0)
 {
@@ -263,8 +290,8 @@ __device__ __forceinline__ void run_item(TL *lds, cptr<int32_t> hdr, const int4 
         load_image<K, NW, TSrc, TL>(lds, ent, nload, hdr[24], reinterpret_cast<const TSrc *>(src),
                                     job, s0, wave, lane);
     } else {
-        load_rows<K, NW, TL>(lds, ent, nload, reinterpret_cast<const TL *>(src), H, s0, wave,
-                             lane);
+        load_rows<K, NW, TSrc, TL>(lds, ent, nload, reinterpret_cast<const TSrc *>(src), H, s0,
+                                   wave, lane);
         __builtin_amdgcn_s_waitcnt(0);  // direct-to-LDS loads have landed
     }
 
@@ -284,19 +311,18 @@ __device__ __forceinline__ void run_item(TL *lds, cptr<int32_t> hdr, const int4 
     __syncthreads();
 
     const bool unmirror = (job.flags & JF_FINAL) && (job.flags & JF_MIRROR);
-    store_rows<K, NW, TL, TAcc>(lds, step_ent, nstore, reinterpret_cast<TAcc *>(dst), H, s0,
-                                unmirror, wave, lane);
+    store_rows<K, NW, TL, TD>(lds, step_ent, nstore, reinterpret_cast<TD *>(dst), H, s0,
+                              unmirror, wave, lane);
 }
 
-// TL: LDS element type (16-bit for the first pass of uint8 images, whose
-// sums of at most 64 lanes stay below 2^16; otherwise the accumulator type).
+// TSrc / TL / TD: element types read, kept in LDS and written (see Combo).
 // TABLE: jobs come from a device table (batches) instead of kernel arguments.
 //
 // Workgroup b runs item (b mod 8) * ceil(n / 8) + b / 8: workgroups are
 // dealt to the eight XCDs round robin, so this gives each XCD a contiguous
 // range of items and neighbouring tiles, which read overlapping rows, share
 // an L2.
-template <int NT, typename TSrc, typename TL, typename TAcc, bool FROM_IMAGE, bool TABLE>
+template <int NT, typename TSrc, typename TL, typename TD, bool FROM_IMAGE, bool TABLE>
 __global__ void __launch_bounds__(NT) fht_pass_kernel(PassArgs args, int n_items)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -316,60 +342,50 @@ __global__ void __launch_bounds__(NT) fht_pass_kernel(PassArgs args, int n_items
     if (job.flags & JF_DST_WS) dst = args.ws + reinterpret_cast<uintptr_t>(job.dst);
 
     switch (hdr[26]) {
-    case 1: run_item<NT, 1, TSrc, TL, TAcc, FROM_IMAGE>(lds, hdr, ent, job, src, dst, item.z); break;
-    case 2: run_item<NT, 2, TSrc, TL, TAcc, FROM_IMAGE>(lds, hdr, ent, job, src, dst, item.z); break;
-    case 3: run_item<NT, 3, TSrc, TL, TAcc, FROM_IMAGE>(lds, hdr, ent, job, src, dst, item.z); break;
-    default: run_item<NT, 4, TSrc, TL, TAcc, FROM_IMAGE>(lds, hdr, ent, job, src, dst, item.z); break;
+    case 1: run_item<NT, 1, TSrc, TL, TD, FROM_IMAGE>(lds, hdr, ent, job, src, dst, item.z); break;
+    case 2: run_item<NT, 2, TSrc, TL, TD, FROM_IMAGE>(lds, hdr, ent, job, src, dst, item.z); break;
+    case 3: run_item<NT, 3, TSrc, TL, TD, FROM_IMAGE>(lds, hdr, ent, job, src, dst, item.z); break;
+    default: run_item<NT, 4, TSrc, TL, TD, FROM_IMAGE>(lds, hdr, ent, job, src, dst, item.z); break;
     }
 }
 
-template <int NT, typename TSrc, typename TFirst, typename TAcc>
-hipError_t launch_nt(bool from_image, const PassArgs &args, int n_items, int lds_bytes,
-                     hipStream_t stream)
+template <int NT, typename TSrc, typename TL, typename TD, bool FROM_IMAGE>
+hipError_t launch_nt(const PassArgs &args, int n_items, int lds_bytes, hipStream_t stream)
 {
     const dim3 grid((n_items + 7) / 8 * 8), block(NT);
-    const bool table = args.jobs != nullptr;
-    if (from_image) {
-        if (table)
-            fht_pass_kernel<NT, TSrc, TFirst, TAcc, true, true><<<grid, block, lds_bytes, stream>>>(args, n_items);
-        else
-            fht_pass_kernel<NT, TSrc, TFirst, TAcc, true, false><<<grid, block, lds_bytes, stream>>>(args, n_items);
-    } else {
-        if (table)
-            fht_pass_kernel<NT, TAcc, TAcc, TAcc, false, true><<<grid, block, lds_bytes, stream>>>(args, n_items);
-        else
-            fht_pass_kernel<NT, TAcc, TAcc, TAcc, false, false><<<grid, block, lds_bytes, stream>>>(args, n_items);
-    }
+    if (args.jobs)
+        fht_pass_kernel<NT, TSrc, TL, TD, FROM_IMAGE, true><<<grid, block, lds_bytes, stream>>>(args, n_items);
+    else
+        fht_pass_kernel<NT, TSrc, TL, TD, FROM_IMAGE, false><<<grid, block, lds_bytes, stream>>>(args, n_items);
     return hipGetLastError();
 }
 
-template <typename TSrc, typename TFirst, typename TAcc>
-hipError_t launch_typed(bool from_image, const PassArgs &args, int n_items, int lds_bytes,
-                        int threads, hipStream_t stream)
+template <typename TSrc, typename TL, typename TD, bool FROM_IMAGE>
+hipError_t launch_typed(const PassArgs &args, int n_items, int lds_bytes, int threads,
+                        hipStream_t stream)
 {
-    switch (threads) {
-    case 512: return launch_nt<512, TSrc, TFirst, TAcc>(from_image, args, n_items, lds_bytes, stream);
-    case 1024: return launch_nt<1024, TSrc, TFirst, TAcc>(from_image, args, n_items, lds_bytes, stream);
-    default: return launch_nt<256, TSrc, TFirst, TAcc>(from_image, args, n_items, lds_bytes, stream);
-    }
+    if (threads == 512)
+        return launch_nt<512, TSrc, TL, TD, FROM_IMAGE>(args, n_items, lds_bytes, stream);
+    return launch_nt<256, TSrc, TL, TD, FROM_IMAGE>(args, n_items, lds_bytes, stream);
 }
 
 }  // namespace
 
-hipError_t launch_pass(Dt dt, bool from_image, const PassArgs &args, int n_items,
-                       int lds_bytes, int threads, hipStream_t stream)
+hipError_t launch_pass(Combo combo, const PassArgs &args, int n, int lds, int threads,
+                       hipStream_t stream)
 {
-    if (n_items <= 0) return hipSuccess;
-    switch (dt) {
-    case Dt::U8:
-        return launch_typed<uint8_t, uint16_t, int32_t>(from_image, args, n_items, lds_bytes,
-                                                        threads, stream);
-    case Dt::F32:
-        return launch_typed<float, float, float>(from_image, args, n_items, lds_bytes, threads,
-                                                 stream);
-    case Dt::F64:
-        return launch_typed<double, double, double>(from_image, args, n_items, lds_bytes, threads,
-                                                    stream);
+    if (n <= 0) return hipSuccess;
+    switch (combo) {
+    case Combo::U8_U16_U16: return launch_typed<uint8_t, uint16_t, uint16_t, true>(args, n, lds, threads, stream);
+    case Combo::U8_U16_I32: return launch_typed<uint8_t, uint16_t, int32_t, true>(args, n, lds, threads, stream);
+    case Combo::U16_U16_U16: return launch_typed<uint16_t, uint16_t, uint16_t, false>(args, n, lds, threads, stream);
+    case Combo::U16_U16_I32: return launch_typed<uint16_t, uint16_t, int32_t, false>(args, n, lds, threads, stream);
+    case Combo::U16_I32_I32: return launch_typed<uint16_t, int32_t, int32_t, false>(args, n, lds, threads, stream);
+    case Combo::I32_I32_I32: return launch_typed<int32_t, int32_t, int32_t, false>(args, n, lds, threads, stream);
+    case Combo::F32_FIRST: return launch_typed<float, float, float, true>(args, n, lds, threads, stream);
+    case Combo::F32_LATER: return launch_typed<float, float, float, false>(args, n, lds, threads, stream);
+    case Combo::F64_FIRST: return launch_typed<double, double, double, true>(args, n, lds, threads, stream);
+    case Combo::F64_LATER: return launch_typed<double, double, double, false>(args, n, lds, threads, stream);
     }
     return hipErrorInvalidValue;
 }

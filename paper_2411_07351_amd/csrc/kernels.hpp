@@ -36,13 +36,26 @@ struct PassArgs {
     JobDesc inl[kInlineJobs];
 };
 
-enum class Dt { U8 = 0, F32 = 1, F64 = 2 };
+// Element types of one fused pass: what it reads (the image in a first pass,
+// the previous pass's rows otherwise), what it keeps in LDS, what it writes.
+// uint8 images keep 16-bit sums while nodes are at most 257 lanes wide
+// (255 * 257 < 2^16), so those intermediates move half the bytes.
+enum class Combo {
+    U8_U16_U16,    // first pass, uint8 image, 16-bit rows out
+    U8_U16_I32,    // first pass, uint8 image, final int32 output
+    U16_U16_U16,   // later pass, 16-bit in and out
+    U16_U16_I32,   // later pass, 16-bit in, final int32 output
+    U16_I32_I32,   // later pass, 16-bit in, 32-bit sums
+    I32_I32_I32,   // later pass, 32-bit
+    F32_FIRST,     // first pass, float32 image
+    F32_LATER,
+    F64_FIRST,     // first pass, float64 image
+    F64_LATER,
+};
 
-// Enqueues one fused pass of `n_items` work items with `threads` (256, 512
-// or 1024) threads per workgroup.  from_image selects the first-pass loader
-// (reads the image of dtype dt), otherwise the pass reads accumulator rows.
-// Returns the launch status.
-hipError_t launch_pass(Dt dt, bool from_image, const PassArgs &args, int n_items,
-                       int lds_bytes, int threads, hipStream_t stream);
+// Enqueues one fused pass of `n_items` work items with `threads` (256 or
+// 512) threads per workgroup.  Returns the launch status.
+hipError_t launch_pass(Combo combo, const PassArgs &args, int n_items, int lds_bytes, int threads,
+                       hipStream_t stream);
 
 }  // namespace fht

@@ -269,6 +269,7 @@ void build_pass(const Tree &tr, int lin, int lout, int T, int S, int K, int pad,
     collect_frontier(tr, 0, lout, &roots);
     for (int r : roots) {
         const int w = tr.nodes[r].w;
+        pass->max_root_w = std::max(pass->max_root_w, w);
         const int tt = (T <= 0) ? w : T;
         for (int ta = 0; ta < w; ta += tt) {
             const int prog = static_cast<int>(pass->hdrs.size() / kHdrInts);
@@ -302,10 +303,21 @@ void build_pass_fitted(const Tree &tr, int lin, int lout, int T, int target, int
 
 }  // namespace
 
-bool plan_axis(int W, int H, int split, int first_bytes, int rest_bytes, const Schedule &sched,
+// Widest node of the frontier of `level`.
+static int frontier_width(const Tree &tr, int level)
+{
+    std::vector<int> roots;
+    collect_frontier(tr, 0, level, &roots);
+    int w = 0;
+    for (int r : roots) w = std::max(w, tr.nodes[r].w);
+    return w;
+}
+
+bool plan_axis(int W, int H, int split, const ElemRule &rule, const Schedule &sched,
                AxisPlan *out, std::string *err)
 {
-    if (W < 1 || H < 1 || (split != 0 && split != 1) || first_bytes <= 0 || rest_bytes <= 0) {
+    if (W < 1 || H < 1 || (split != 0 && split != 1) || rule.narrow_bytes <= 0 ||
+        rule.wide_bytes <= 0) {
         if (err) *err = "bad axis arguments";
         return false;
     }
@@ -317,9 +329,6 @@ bool plan_axis(int W, int H, int split, int first_bytes, int rest_bytes, const S
     out->passes.clear();
     int lin = 0;
     do {
-        const int eb = lin == 0 ? first_bytes : rest_bytes;
-        const int budget_elems = sched.lds_budget / eb;
-        const int pad = eb == 2 ? 2 : 1;  // one 32-bit bank (two for 64-bit elements)
         const int maxlv = (lin == 0) ? std::min(sched.first_levels, kMaxFirstLevels)
                                      : std::min(sched.max_levels, kMaxSteps);
         const int target = (lin == 0) ? sched.s_tile_first : sched.s_tile;
@@ -328,15 +337,24 @@ bool plan_axis(int W, int H, int split, int first_bytes, int rest_bytes, const S
         const int hi = std::min(L, lin + maxlv);
         const int lo = (L > lin) ? lin + 1 : lin;
         for (int lout = hi; lout >= lo && !found; --lout) {
+            const int eb = rule.bytes_for(frontier_width(tr, lout));
+            const int budget_elems = sched.lds_budget / eb;
+            const int pad = eb == 2 ? 2 : 1;  // skew rows by one 32-bit bank
             // The first pass takes whole roots (at most 64 lanes, loaded as one
             // lane x window rectangle).
             std::vector<int> tiles;
             if (lin == 0) tiles = {0};
-            else if (sched.t_tile > 0) tiles = {sched.t_tile};
-            else tiles = {0, 64, 32, 16, 8, 4};
+            else if (sched.t_tile > 0) {
+                // the requested slope tile, halved until the pass fits
+                for (int T = sched.t_tile; T >= 4; T /= 2) tiles.push_back(T);
+                if (tiles.empty()) tiles.push_back(sched.t_tile);
+            } else {
+                tiles = {32, 16, 8, 4};
+            }
             for (int T : tiles) {
                 Pass p;
                 build_pass_fitted(tr, lin, lout, T, target, pad, H, &p);
+                p.elem_bytes = eb;
                 if (p.fits && p.max_lds_elems <= budget_elems) {
                     best = std::move(p);
                     found = true;

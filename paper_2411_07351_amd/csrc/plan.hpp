@@ -43,13 +43,14 @@ Tree make_tree(int W, int split);
 // Row windows are tiled in 64-position chunks; a pass picks the largest
 // position tile whose widest window fits its target width.
 struct Schedule {
-    int s_tile = 128;         // target window width, later passes
+    int s_tile = 192;         // target window width, later passes
     int s_tile_first = 192;   // target window width, first pass
     int first_levels = 5;
-    int max_levels = 6;
+    int max_levels = 3;
     int lds_budget = 64 * 1024;
-    int t_tile = 0;           // 0: try 64, 32, 16, 8
-    int threads = 256;        // threads per workgroup: 256, 512 or 1024
+    int t_tile = 16;          // 0: the largest of 32, 16, 8, 4 that fits
+    int threads = 256;        // threads per workgroup of later passes: 256 or 512
+    int threads_first = 256;  // threads per workgroup of the first pass
 };
 
 // One fused pass: from the frontier of level lin (maximal nodes of height
@@ -59,6 +60,8 @@ struct Pass {
     int t_tile = 0;
     int S = 0;                   // positions per work item
     int widest = 0;              // widest row window
+    int max_root_w = 0;          // widest node this pass produces
+    int elem_bytes = 4;          // LDS element size
     int max_lds_elems = 0;
     bool fits = true;            // every program respects the kernel's prefetch limits
     std::vector<int32_t> hdrs;   // kHdrInts per program
@@ -71,10 +74,17 @@ struct AxisPlan {
     std::vector<Pass> passes;
 };
 
-// Plans the passes for W lanes of H positions.  first_bytes and rest_bytes are
-// the LDS element sizes of the first pass and of the later passes.  Returns
-// false and sets *err on failure.
-bool plan_axis(int W, int H, int split, int first_bytes, int rest_bytes, const Schedule &sched,
+// LDS element size of a pass as a function of the widest node it produces:
+// `narrow_bytes` while that width is at most `narrow_width`, else `wide_bytes`
+// (uint8 images: 16-bit sums up to 257 lanes, then 32-bit).
+struct ElemRule {
+    int narrow_bytes = 4, wide_bytes = 4, narrow_width = 0;
+    int bytes_for(int width) const { return width <= narrow_width ? narrow_bytes : wide_bytes; }
+};
+
+// Plans the passes for W lanes of H positions.  Returns false and sets *err
+// on failure.
+bool plan_axis(int W, int H, int split, const ElemRule &rule, const Schedule &sched,
                AxisPlan *out, std::string *err);
 
 }  // namespace fht

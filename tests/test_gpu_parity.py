@@ -159,3 +159,51 @@ def test_batch_matches_plain(F):
             ref = native.hough4_u8(img_np, split)
             for q, g in enumerate(p.split_out(out)):
                 assert (g.cpu().numpy() == ref[q]).all(), (img_np.shape, q)
+
+
+@pytest.mark.parametrize("sched", [None,
+                                   dict(first_levels=5, max_levels=4, t_tile=16),
+                                   dict(first_levels=4, max_levels=5, t_tile=8),
+                                   dict(first_levels=5, max_levels=3, t_tile=32, threads=256)])
+def test_u16_intermediates_at_full_range(F, sched):
+    # uint8 images keep 16-bit sums while nodes are at most 257 lanes wide;
+    # 255 * 257 = 65535 is the largest such sum.  Saturated images hit it.
+    for R, C in ((514, 33), (33, 514), (257, 70), (1021, 64)):
+        img = np.full((R, C), 255, dtype=np.uint8)
+        got = _gpu_hough(F, img, 0, sched)
+        for q, (W, H) in enumerate(((R, C), (R, C), (C, R), (C, R))):
+            assert (got[q] == 255 * W).all(), (R, C, q)
+        rng = WL.rng_for(0, salt=10)
+        img = rng.integers(200, 256, size=(R, C), dtype=np.uint8)
+        got = _gpu_hough(F, img, 1, sched)
+        ref = native.hough4_u8(img, 1)
+        for q in range(4):
+            assert (got[q] == ref[q]).all(), (R, C, q)
+
+
+def test_graph_replays_match_eager(F):
+    # A captured batch must give the eager result on every replay, with eager
+    # work and synchronisations between replays.
+    rng = WL.rng_for(3, salt=2)
+    imgs_np = WL.ragged_edge_maps(rng, 10, 8, 300)
+    imgs = [torch.from_numpy(i).cuda() for i in imgs_np]
+    plans = [F.Plan(i.shape[0], i.shape[1], "u8", "S") for i in imgs]
+    outs = [p.new_out() for p in plans]
+    batch = F.Batch(plans, imgs, outs)
+    ws = batch.new_ws()
+    batch.run(ws)
+    torch.cuda.synchronize()
+    eager = [o.clone() for o in outs]
+    graph = batch.capture(ws)
+    for rep in range(4):
+        for o in outs:
+            o.fill_(-1)
+        junk = torch.randn(1 << 20, device="cuda") * 2.0  # unrelated eager work
+        graph.replay()
+        torch.cuda.synchronize()
+        del junk
+        for o, e in zip(outs, eager):
+            assert torch.equal(o, e), rep
+    ref = native.hough4_u8(imgs_np[3], 0)
+    for q, g in enumerate(plans[3].split_out(outs[3])):
+        assert (g.cpu().numpy() == ref[q]).all()
