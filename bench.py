@@ -127,16 +127,11 @@ def main():
     info = [F.fht_plan_launch_info(plan.handle, l) for l in range(nl)]
     px_per_step = n * R * C
 
-    def plain_step(events=None):
+    def plain_step():
         for i in range(n):
             ip, op = imgs[i].data_ptr(), outs[i].data_ptr()
             for l in range(nl):
-                if events is not None:
-                    events[l].append(_events(torch))
-                    events[l][-1][0].record(stream)
                 F.fht_forward_launch(plan.handle, l, ip, op, ws.data_ptr(), sh)
-                if events is not None:
-                    events[l][-1][1].record(stream)
 
     for _ in range(args.warmup):
         plain_step()
@@ -155,15 +150,23 @@ def main():
     plain_s = time.perf_counter() - t0
     plain_event_ms = a.elapsed_time(b) / args.steps
 
-    # Kernel durations: the same K steps again with every launch bracketed by
-    # events (the events add launch gaps, so this loop is not the headline).
+    # Kernel durations: for each launch of the plan, the n images' launches
+    # back to back between one pair of events on the same stream, K times.
+    # Back-to-back launches of one kernel leave only the hardware's dispatch
+    # gap between them, so the mean is the kernel's average duration.
     events = [[] for _ in range(nl)]
     for _ in range(args.steps):
-        plain_step(events)
+        for l in range(nl):
+            e = _events(torch)
+            e[0].record(stream)
+            for i in range(n):
+                F.fht_forward_launch(plan.handle, l, imgs[i].data_ptr(), outs[i].data_ptr(),
+                                     ws.data_ptr(), sh)
+            e[1].record(stream)
+            events[l].append(e)
     torch.cuda.synchronize()
-    launch_ms = [float(np.mean([x.elapsed_time(y) for x, y in ev])) for ev in events]
-    totals = [m * len(ev) for m, ev in zip(launch_ms, events)]
-    dom = int(np.argmax(totals))
+    launch_ms = [float(np.mean([x.elapsed_time(y) for x, y in ev])) / n for ev in events]
+    dom = int(np.argmax(launch_ms))
     dom_bytes = info[dom]["bytes_in"] + info[dom]["bytes_out"]
     achieved = dom_bytes / (launch_ms[dom] * 1e-3) / 1e9
     kernels = ["fht_pass_kernel<256, unsigned char, unsigned short, unsigned short, true, false>",
