@@ -44,6 +44,12 @@ def _parse():
     ap.add_argument("--ragged", type=int, default=512, help="images in the ragged batch (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU oracle sample budget (0 disables the cpu_baseline leg)")
+    ap.add_argument("--diff-images", type=int, default=32,
+                    help="float32 384x257 images of the forward+adjoint leg (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=300,
+                    help="requests per serving run (0: skip the serving leg)")
+    ap.add_argument("--serve-qps", type=float, default=200.0,
+                    help="the fixed absolute request rate of the serving leg")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -90,6 +96,108 @@ def _cpu_baseline(imgs_np, split: int, budget_s: float):
             "cores": native.num_threads(), "kind": "oracle",
             "sample": f"{done} of {len(imgs_np)} images {R}x{C}, 4 quadrants, direct sums along "
                       f"the generating patterns (C, OpenMP), {dt:.1f} s"}
+
+
+def _serving(args, torch, F, WL):
+    """Poisson request stream through the continuous-batching server: a
+    closed burst measures capacity, then Poisson arrivals at 50 % and 80 % of
+    it and at a fixed rate give p50/p99 latency (arrival to completion)."""
+    import numpy as np
+
+    from paper_2411_07351_amd import serving as S
+
+    n = args.serve_requests
+    items = WL.serving_requests(WL.rng_for(5), n, 64, 4096)
+    imgs = [torch.from_numpy(img).pin_memory() for _, img in items]
+    warm = WL.serving_requests(WL.rng_for(5, salt=1), 16, 64, 1024)
+    warm_imgs = [torch.from_numpy(img).pin_memory() for _, img in warm]
+    cfg = dict(max_batch_images=64, max_batch_px=32 << 20, depth=2,
+               plan_threads=min(16, os.cpu_count() or 1), keep_outputs=False)
+    budget = 32 << 30
+
+    def run(images, arrivals):
+        reqs = [S.Request(i, im, float(t)) for i, (im, t) in enumerate(zip(images, arrivals))]
+        srv = S.Server(S.GpuExecutor(streams=2), budget, **cfg)
+        try:
+            srv.run(reqs)
+        finally:
+            srv.close()
+        torch.cuda.synchronize()
+        out = S.summarize(reqs)
+        out["peak_admitted_gb"] = round(srv.peak_in_use / 1e9, 2)
+        out["batches"] = srv.batches
+        out["max_batch"] = max(srv.batch_sizes) if srv.batch_sizes else 0
+        return out
+
+    run(warm_imgs, np.zeros(len(warm_imgs)))
+    cap = run(imgs, np.zeros(n))
+    rng = np.random.default_rng(WL.SEED_BASE + 5 + 7)
+    runs = []
+    for label, qps in (("50% of capacity", 0.5 * cap["req_per_s"]),
+                       ("80% of capacity", 0.8 * cap["req_per_s"]),
+                       ("fixed", args.serve_qps)):
+        res = run(imgs, WL.poisson_arrivals(rng, n, qps))
+        runs.append({"qps": round(qps, 1), "load": label, **res})
+    shapes = [tuple(im.shape) for im in imgs]
+    return {
+        "workload": f"{n} requests, sides log-uniform in [64, 4096], 70% uint8 edge maps / "
+                    "30% float32 N(0,1), Poisson arrivals, 4 quadrants, FHT2DS",
+        "mpixels": round(sum(r * c for r, c in shapes) / 1e6, 1),
+        "u8_requests": sum(k == "u8" for k, _ in items),
+        "hbm_budget_gb": budget / 1e9,
+        "streams": 2, **{k: v for k, v in cfg.items() if k != "keep_outputs"},
+        "capacity": cap,
+        "runs": runs,
+    }
+
+
+def _differentiable(args, torch, F, WL):
+    """Forward transform plus hand-written adjoint (the backward pass of
+    ``HoughFunction``) of float32 384 x 257 N(0,1) images, per image."""
+    import numpy as np
+
+    n, R, C = args.diff_images, 384, 257
+    rng = WL.rng_for(4)
+    imgs = torch.from_numpy(np.stack([WL.normal_f32(rng, R, C) for _ in range(n)])).cuda()
+    plan = F.Plan(R, C, "f32", "S")
+    outs = torch.empty((n, plan.out_elems), dtype=torch.float32, device="cuda")
+    gouts = torch.from_numpy(rng.standard_normal((n, plan.out_elems)).astype(np.float32)).cuda()
+    gimgs = torch.empty_like(imgs)
+    fws = plan.new_ws("cuda")
+    aws = torch.empty(max(F.fht_plan_adjoint_workspace_bytes(plan.handle), 1), dtype=torch.uint8,
+                      device="cuda")
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+
+    def fwd():
+        for i in range(n):
+            F.fht_forward(plan.handle, imgs[i].data_ptr(), outs[i].data_ptr(), fws.data_ptr(), sh)
+
+    def bwd():
+        for i in range(n):
+            F.fht_adjoint(plan.handle, gouts[i].data_ptr(), gimgs[i].data_ptr(), aws.data_ptr(), sh)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        a, b = _events(torch)
+        a.record(stream)
+        for _ in range(args.steps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / args.steps
+
+    f_ms, b_ms = timed(fwd), timed(bwd)
+    fb_ms = timed(lambda: (fwd(), bwd()))
+    px = n * R * C
+    return {"workload": f"{n} float32 {R}x{C} N(0,1) images, forward + adjoint, 4 quadrants, "
+                        "per-image launches",
+            "value": round(px / (fb_ms * 1e-3) / 1e6, 1), "unit": "Mpixel/s",
+            "forward_ms": round(f_ms, 4), "adjoint_ms": round(b_ms, 4),
+            "forward_adjoint_ms": round(fb_ms, 4),
+            "adjoint_launches_per_image": max(F.fht_plan_adjoint_tasks(plan.handle, v).shape[0]
+                                              for v in (0, 1)) + 1}
 
 
 def _events(torch):
@@ -302,6 +410,12 @@ def main():
                       "ms_per_step": round(rpms, 3)},
         }
         del rgraph, rb, rws, routs, rimgs
+
+    if args.diff_images > 0:
+        result["differentiable"] = _differentiable(args, torch, F, WL)
+
+    if args.serve_requests > 0:
+        result["serving"] = _serving(args, torch, F, WL)
 
     if args.copy_mib > 0:
         # A plain device copy of known size, for calibrating byte counters.

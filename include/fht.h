@@ -171,7 +171,88 @@ int32_t fht_batch_num_launches(fht_batch batch);
 fht_status fht_batch_run(fht_batch batch, void *d_ws, void *stream);
 /* One launch of fht_batch_run (0 <= launch < fht_batch_num_launches). */
 fht_status fht_batch_run_launch(fht_batch batch, int32_t launch, void *d_ws, void *stream);
+/* Frees the batch and, for fht_batch_create, its device tables (a device
+ * synchronisation point).  A batch whose tables went to caller memory with
+ * fht_batch_upload frees host memory only. */
 void fht_batch_destroy(fht_batch batch);
+
+/*
+ * The same batch in two halves, for callers that must not allocate or
+ * synchronise the device while other work runs (a serving loop):
+ * fht_batch_prepare builds the work list in host memory only (same arguments
+ * and errors as fht_batch_create, no FHT_ENODEV); fht_batch_tables_bytes is the
+ * size of its device tables; fht_batch_upload enqueues their copy into
+ * caller-owned device memory d_tables (at least that many bytes, 256-byte
+ * aligned) on `stream`.  fht_batch_run on that stream (or one ordered after
+ * it) then runs the batch.  The caller keeps d_tables alive while the batch
+ * runs, and destroys the batch only after the copy has completed (the copy
+ * reads the batch's host memory).  A batch can be uploaded once; fht_batch_run
+ * before the upload returns FHT_EINVAL.
+ * Errors of fht_batch_upload: FHT_EINVAL (null, too small, already owning
+ * tables), FHT_EHIP.
+ */
+fht_status fht_batch_prepare(fht_batch *out, const fht_plan *plans, int32_t n,
+                             const void *const *d_imgs, void *const *d_outs);
+size_t fht_batch_tables_bytes(fht_batch batch);
+fht_status fht_batch_upload(fht_batch batch, void *d_tables, size_t bytes, void *stream);
+
+/*
+ * Adjoint (back-projection) of fht_forward for float32/float64 plans: the
+ * image gradient of a scalar function of the output, given its output
+ * gradient.  With out_q[t][s] = sum_x A_q[x][(s + sigma_q pat_t(x)) mod H]
+ * (Alg. 2 patterns; A_q the lane view of quadrant q, sigma = +1 for V+/H+,
+ * -1 for V-/H-), it computes
+ *   gimg = sum_q view_q^T ( g_q[x][y] = sum_t gout_q[t][(y - sigma_q pat_t(x)) mod H] )
+ * by running the merges of Alg. 1 backwards, one tree level per launch.
+ *   d_gout device, fht_plan_out_elems elements in fht_forward's output layout
+ *   d_gimg device, rows x cols, overwritten
+ *   d_ws   device, fht_plan_adjoint_workspace_bytes bytes (NULL when 0)
+ * Asynchronous.  Errors: FHT_EDTYPE (uint8 plan), FHT_EINVAL, FHT_ENODEV,
+ * FHT_ENOMEM, FHT_EHIP.
+ */
+size_t fht_plan_adjoint_workspace_bytes(fht_plan plan);
+/* Host view of the adjoint's gather steps of lane view v (0: lanes are rows,
+ * 1: columns), valid while the plan lives: *levels steps of *lanes tasks of 4
+ * ints {p0, n, r0, right}; step k, row x:
+ *   g_out[x][s] = sum_{j<n} g_in[p0 + j][(s - (right ? r0 + j : 0)) mod H].
+ * Errors: FHT_EINVAL, FHT_EDTYPE (uint8 plan). */
+fht_status fht_plan_adjoint_tasks(fht_plan plan, int32_t v, const int32_t **tasks,
+                                  int32_t *levels, int32_t *lanes);
+fht_status fht_adjoint(fht_plan plan, const void *d_gout, void *d_gimg, void *d_ws, void *stream);
+
+/*
+ * Peak finding on the quadrant outputs of one image (the step after the
+ * transform: a straight segment concentrates on one output, Sec. 3).
+ * A candidate is an output out_q[t][s] >= min_value that is a strict maximum
+ * of its (2 radius + 1)^2 window in (t, s) of quadrant q (s wraps mod H, t is
+ * clipped to [0, W)); an equal neighbour earlier in the flat output order
+ * wins the tie.  The k strongest candidates (value descending, then flat
+ * output index ascending) go to d_peaks.
+ *   d_out     device, the plan's output (fht_forward layout, NaN-free)
+ *   k         1..4096 peaks wanted; radius 0..64; capacity k..2^26 candidates kept
+ *   d_ws      device, fht_peaks_workspace_bytes(capacity) bytes
+ *   d_peaks   device, k fht_peak records (value as float)
+ *   d_found   device, 2 int32: peaks written, candidates found (more than
+ *             capacity means some were dropped: raise min_value or capacity)
+ * Asynchronous.  Errors: FHT_EINVAL, FHT_ENODEV, FHT_EHIP.
+ */
+typedef struct fht_peak {
+    float value;
+    int32_t quadrant, t, s;
+} fht_peak;
+size_t fht_peaks_workspace_bytes(int32_t capacity);
+fht_status fht_peaks(fht_plan plan, const void *d_out, int32_t k, int32_t radius,
+                     double min_value, int32_t capacity, void *d_ws, fht_peak *d_peaks,
+                     int32_t *d_found, void *stream);
+
+/*
+ * Fault injection for tests of error handling: the next `count` calls that
+ * enqueue device work (fht_forward, fht_forward_launch, fht_adjoint, fht_peaks,
+ * fht_batch_upload, fht_batch_run, fht_batch_run_launch) return `code` after checking their
+ * arguments and before enqueuing anything.  count <= 0 or code == FHT_OK
+ * disarms it.  Process-wide; safe to call from any thread.
+ */
+void fht_debug_fail_next(fht_status code, int32_t count);
 
 /*
  * Host view of a plan's tables, for inspection and tests of the planner.

@@ -244,6 +244,40 @@ def explicit_matrix(W: int, H: int, split: int, sigma: int = 1) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
+# The adjoint (back-projection).  The transform is linear: hough_lanes sends
+# A to J with J[t][s] = sum_x A[x][(s + sigma pat_t(x)) mod H], so the pixel
+# A[x][y] enters J[t][s] exactly for s = (y - sigma pat_t(x)) mod H.  The
+# adjoint therefore sends a gradient G on the output back along the same
+# patterns (Alg. 2).
+# ---------------------------------------------------------------------------
+
+def adjoint_lanes(G: np.ndarray, split: int, sigma: int = 1) -> np.ndarray:
+    """``gA[x][y] = sum_t G[t][(y - sigma * pat_{W,t}(x)) mod H]`` in float64."""
+    G = np.asarray(G, dtype=np.float64)
+    W, H = G.shape
+    P = patterns(W, split)
+    y = np.arange(H)
+    out = np.zeros((W, H), dtype=np.float64)
+    for x in range(W):
+        for t in range(W):
+            out[x] += G[t][(y - sigma * int(P[t, x])) % H]
+    return out
+
+
+def adjoint4(Gs, split: int, shape) -> np.ndarray:
+    """Image gradient of the quadrant images: ``Gs`` maps quadrant q to its
+    output gradient (W_q x H_q); each view's adjoint is mapped back to the
+    row-major R x C image (column-lane views transposed) and summed."""
+    R, C = shape
+    g = np.zeros((R, C), dtype=np.float64)
+    sig = {0: 1, 1: -1, 2: 1, 3: -1}
+    for q, G in Gs.items():
+        gA = adjoint_lanes(G, split, sig[q])
+        g += gA if q < 2 else gA.T
+    return g
+
+
+# ---------------------------------------------------------------------------
 # Sec. 4: addition counts (Theorem 1) and orthotropic error (Theorem 2)
 # ---------------------------------------------------------------------------
 

@@ -17,7 +17,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libfht.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2411_07351_amd.build`")
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2411_07351_amd/build.py`")
 
 # torch first: the library must bind to the HIP runtime torch already loaded,
 # because streams and device pointers are torch's.
@@ -33,6 +33,9 @@ __all__ = [
     "fht_plan_launch_info", "fht_plan_upload", "fht_forward", "fht_forward_launch", "fht_batch_create",
     "fht_batch_workspace_bytes", "fht_batch_num_launches", "fht_batch_run",
     "fht_batch_run_launch", "fht_batch_destroy", "fht_plan_num_passes", "fht_plan_pass_tables",
+    "fht_batch_prepare", "fht_batch_tables_bytes", "fht_batch_upload", "fht_debug_fail_next",
+    "fht_plan_adjoint_workspace_bytes", "fht_plan_adjoint_tasks", "fht_adjoint",
+    "HoughFunction", "hough_autograd", "fht_peaks_workspace_bytes", "fht_peaks", "PEAK_DTYPE",
 ]
 
 FHT_U8, FHT_F32, FHT_F64 = 0, 1, 2
@@ -49,7 +52,14 @@ EXPORTED = (
     "fht_plan_launch_info", "fht_plan_upload", "fht_forward", "fht_forward_launch", "fht_batch_create",
     "fht_batch_workspace_bytes", "fht_batch_num_launches", "fht_batch_run",
     "fht_batch_run_launch", "fht_batch_destroy", "fht_plan_num_passes", "fht_plan_pass_tables",
+    "fht_batch_prepare", "fht_batch_tables_bytes", "fht_batch_upload", "fht_debug_fail_next",
+    "fht_plan_adjoint_workspace_bytes", "fht_plan_adjoint_tasks", "fht_adjoint",
+    "fht_peaks_workspace_bytes", "fht_peaks",
 )
+
+# struct fht_peak
+PEAK_DTYPE = np.dtype([("value", np.float32), ("quadrant", np.int32), ("t", np.int32),
+                       ("s", np.int32)])
 
 
 class fht_schedule(ctypes.Structure):
@@ -92,6 +102,16 @@ _sig("fht_batch_num_launches", _i32, _vp)
 _sig("fht_batch_run", _i32, _vp, _vp, _vp)
 _sig("fht_batch_run_launch", _i32, _vp, _i32, _vp, _vp)
 _sig("fht_batch_destroy", None, _vp)
+_sig("fht_batch_prepare", _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i32,
+     ctypes.POINTER(_vp), ctypes.POINTER(_vp))
+_sig("fht_batch_tables_bytes", _sz, _vp)
+_sig("fht_batch_upload", _i32, _vp, _vp, _sz, _vp)
+_sig("fht_debug_fail_next", None, _i32, _i32)
+_sig("fht_plan_adjoint_workspace_bytes", _sz, _vp)
+_sig("fht_plan_adjoint_tasks", _i32, _vp, _i32, _ppi32, _pi32, _pi32)
+_sig("fht_adjoint", _i32, _vp, _vp, _vp, _vp, _vp)
+_sig("fht_peaks_workspace_bytes", _sz, _i32)
+_sig("fht_peaks", _i32, _vp, _vp, _i32, _i32, ctypes.c_double, _i32, _vp, _vp, _vp, _vp)
 _sig("fht_plan_num_passes", _i32, _vp, _i32)
 _sig("fht_plan_pass_tables", _i32, _vp, _i32, _i32, _ppi32, _pi32, _ppi32, _pi32, _ppi32,
      _pi32, _pi32)
@@ -174,6 +194,27 @@ def fht_batch_create(plans: Sequence[int], d_imgs: Sequence[int], d_outs: Sequen
     return h.value
 
 
+def fht_batch_prepare(plans: Sequence[int], d_imgs: Sequence[int], d_outs: Sequence[int]) -> int:
+    n = len(plans)
+    arr = ctypes.c_void_p * n
+    h = _vp()
+    _check(_lib.fht_batch_prepare(ctypes.byref(h), arr(*plans), n, arr(*d_imgs), arr(*d_outs)),
+           "fht_batch_prepare")
+    return h.value
+
+
+def fht_batch_tables_bytes(batch: int) -> int:
+    return _lib.fht_batch_tables_bytes(batch)
+
+
+def fht_batch_upload(batch: int, d_tables: int, nbytes: int, stream: int | None) -> None:
+    _check(_lib.fht_batch_upload(batch, d_tables, nbytes, stream), "fht_batch_upload")
+
+
+def fht_debug_fail_next(code: int, count: int = 1) -> None:
+    _lib.fht_debug_fail_next(code, count)
+
+
 def fht_batch_workspace_bytes(batch: int) -> int:
     return _lib.fht_batch_workspace_bytes(batch)
 
@@ -192,6 +233,35 @@ def fht_batch_run_launch(batch: int, launch: int, d_ws: int | None, stream: int 
 
 def fht_batch_destroy(batch: int) -> None:
     _lib.fht_batch_destroy(batch)
+
+
+def fht_plan_adjoint_workspace_bytes(plan: int) -> int:
+    return _lib.fht_plan_adjoint_workspace_bytes(plan)
+
+
+def fht_plan_adjoint_tasks(plan: int, view: int) -> np.ndarray:
+    """Copy of the adjoint's tasks of one lane view: (levels, lanes, 4) int32."""
+    tasks, levels, lanes = _pi32(), _i32(), _i32()
+    _check(_lib.fht_plan_adjoint_tasks(plan, view, ctypes.byref(tasks), ctypes.byref(levels),
+                                       ctypes.byref(lanes)), "fht_plan_adjoint_tasks")
+    n = levels.value * lanes.value * 4
+    if n == 0:
+        return np.zeros((levels.value, lanes.value, 4), dtype=np.int32)
+    return np.ctypeslib.as_array(tasks, shape=(n,)).reshape(levels.value, lanes.value, 4).copy()
+
+
+def fht_adjoint(plan: int, d_gout: int, d_gimg: int, d_ws: int | None, stream: int | None) -> None:
+    _check(_lib.fht_adjoint(plan, d_gout, d_gimg, d_ws, stream), "fht_adjoint")
+
+
+def fht_peaks_workspace_bytes(capacity: int) -> int:
+    return _lib.fht_peaks_workspace_bytes(capacity)
+
+
+def fht_peaks(plan: int, d_out: int, k: int, radius: int, min_value: float, capacity: int,
+              d_ws: int, d_peaks: int, d_found: int, stream: int | None) -> None:
+    _check(_lib.fht_peaks(plan, d_out, k, radius, min_value, capacity, d_ws, d_peaks, d_found,
+                          stream), "fht_peaks")
 
 
 def fht_plan_num_passes(plan: int, view: int) -> int:
@@ -313,10 +383,78 @@ class Plan:
         return self.split_out(out)
 
 
+    def adjoint(self, gout, gimg=None, ws=None, stream=None):
+        """Image gradient for the output gradient `gout` (flat, fht_forward's
+        output layout; float plans only)."""
+        torch = _torch()
+        if not gout.is_cuda or not gout.is_contiguous() or gout.dtype != self.out_dtype \
+                or gout.numel() < self.out_elems:
+            raise ValueError("output gradient must be a contiguous device tensor of the "
+                             "plan's output size and dtype")
+        if gimg is None:
+            gimg = torch.empty((self.rows, self.cols), dtype=self.in_dtype, device=gout.device)
+        abytes = fht_plan_adjoint_workspace_bytes(self.handle)
+        if ws is None and abytes:
+            ws = torch.empty(abytes, dtype=torch.uint8, device=gout.device)
+        fht_adjoint(self.handle, gout.data_ptr(), gimg.data_ptr(),
+                    ws.data_ptr() if ws is not None else None, _stream_handle(stream))
+        return gimg
+
+
+    def peaks(self, out, k: int = 32, radius: int = 3, min_value: float = 0.0,
+              capacity: int = 1 << 16, stream=None):
+        """The k strongest local maxima of the output `out` (see fht_peaks):
+        a NumPy array of PEAK_DTYPE records, strongest first, and the number
+        of candidates found."""
+        torch = _torch()
+        if not out.is_cuda or not out.is_contiguous() or out.numel() < self.out_elems:
+            raise ValueError("output must be a contiguous device tensor of the plan's size")
+        ws = torch.empty(fht_peaks_workspace_bytes(capacity), dtype=torch.uint8, device=out.device)
+        rec = torch.zeros(k * PEAK_DTYPE.itemsize, dtype=torch.uint8, device=out.device)
+        found = torch.zeros(2, dtype=torch.int32, device=out.device)
+        fht_peaks(self.handle, out.data_ptr(), k, radius, float(min_value), capacity, ws.data_ptr(),
+                  rec.data_ptr(), found.data_ptr(), _stream_handle(stream))
+        if stream is not None:
+            stream.synchronize()
+        n, cands = (int(v) for v in found.cpu())
+        return rec.cpu().numpy().view(PEAK_DTYPE)[:n].copy(), cands
+
+
+class HoughFunction(torch.autograd.Function):
+    """Differentiable forward transform of one float image: returns the flat
+    output (all quadrants); the backward pass is the library's adjoint."""
+
+    @staticmethod
+    def forward(ctx, img, plan):
+        out = plan.new_out(img.device)
+        plan.forward(img.contiguous(), out)
+        ctx.plan = plan
+        return out
+
+    @staticmethod
+    def backward(ctx, gout):
+        return ctx.plan.adjoint(gout.contiguous()), None
+
+
+def hough_autograd(img, split="S", quadrants=(0, 1, 2, 3)) -> list:
+    """`hough` with gradients: one (W, H) tensor per quadrant, views of one
+    flat output whose backward runs ``fht_adjoint``."""
+    key = (tuple(img.shape), img.dtype, _split_code(split), tuple(quadrants))
+    plan = _plan_cache.get(key)
+    if plan is None:
+        plan = Plan(img.shape[0], img.shape[1], img.dtype, split, quadrants)
+        _plan_cache[key] = plan
+    return plan.split_out(HoughFunction.apply(img, plan))
+
+
 class Batch:
     """Many images (one plan each) run as one launch per fused pass."""
 
-    def __init__(self, plans: Sequence[Plan], imgs, outs):
+    def __init__(self, plans: Sequence[Plan], imgs, outs, defer_upload: bool = False):
+        """With ``defer_upload`` the device tables are not allocated here:
+        ``upload(tables, stream)`` copies them into a caller tensor of at least
+        ``tables_bytes`` bytes (nothing here then allocates or synchronises the
+        device)."""
         if not (len(plans) == len(imgs) == len(outs)) or not plans:
             raise ValueError("plans, images and outputs must be non-empty and of equal length")
         for p, img, out in zip(plans, imgs, outs):
@@ -325,10 +463,21 @@ class Batch:
                 raise ValueError("output buffer has the wrong size or dtype")
         self.plans = list(plans)      # keep the plans alive as long as the batch
         self.imgs, self.outs = list(imgs), list(outs)
-        self.handle = fht_batch_create([p.handle for p in plans], [i.data_ptr() for i in imgs],
-                                       [o.data_ptr() for o in outs])
+        make = fht_batch_prepare if defer_upload else fht_batch_create
+        self.handle = make([p.handle for p in plans], [i.data_ptr() for i in imgs],
+                           [o.data_ptr() for o in outs])
         self.ws_bytes = fht_batch_workspace_bytes(self.handle)
         self.num_launches = fht_batch_num_launches(self.handle)
+        self.tables_bytes = fht_batch_tables_bytes(self.handle)
+        self.tables = None
+
+    def upload(self, tables, stream=None) -> None:
+        """Enqueue the copy of the device tables into `tables` (a device tensor
+        of at least ``tables_bytes`` bytes, kept alive with the batch)."""
+        if tables.numel() * tables.element_size() < self.tables_bytes:
+            raise ValueError("table buffer too small")
+        fht_batch_upload(self.handle, tables.data_ptr(), self.tables_bytes, _stream_handle(stream))
+        self.tables = tables
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -83,12 +84,15 @@ struct DevTables {
     int32_t *hdrs = nullptr;
     int32_t *ops = nullptr;
     std::vector<int32_t *> items;  // per launch
+    int32_t *adj[2] = {nullptr, nullptr};  // adjoint tasks per lane view
 };
 
 void free_tables(DevTables &t)
 {
     if (t.hdrs) (void)hipFree(t.hdrs);
     if (t.ops) (void)hipFree(t.ops);
+    for (int32_t *p : t.adj)
+        if (p) (void)hipFree(p);
     for (int32_t *p : t.items)
         if (p) (void)hipFree(p);
     t = DevTables{};
@@ -111,6 +115,9 @@ struct fht_plan_s {
     std::vector<int32_t> hdrs, ops;  // programs of both views, all passes
     std::vector<int> prog_base[2];   // first program of view v, pass p
     std::vector<Launch> launches;    // in level order
+    fht::AdjointAxis adj[2];         // adjoint steps per lane view (float plans)
+    size_t adj_ws_off[4][2] = {};
+    size_t adj_ws_bytes = 0;
     std::mutex mu;
     std::deque<DevTables> dev;  // stable addresses: launches hold pointers into it
 
@@ -145,6 +152,7 @@ struct fht_plan_s {
             e = upload(launches[l].items, &ptr);
             t.items.push_back(ptr);
         }
+        for (int v = 0; e == hipSuccess && v < 2; ++v) e = upload(adj[v].tasks, &t.adj[v]);
         if (e != hipSuccess) {
             free_tables(t);
             return hip_status(e);
@@ -185,26 +193,28 @@ struct fht_plan_s {
     }
 };
 
+// A batch's device work list lives in one table blob: jobs, then program
+// headers, then entries, then the items of every launch, each 256-byte aligned.
+// The blob is built in host memory; it goes to device memory the library
+// allocates (fht_batch_create) or the caller provides (fht_batch_upload).
 struct fht_batch_s {
     fht_dtype dtype = FHT_U8;
     int device = -1;
     size_t ws_bytes = 0;
-    int32_t *hdrs = nullptr;
-    int32_t *ops = nullptr;
-    JobDesc *jobs = nullptr;
+    std::vector<char> blob;
+    size_t off_jobs = 0, off_hdrs = 0, off_ops = 0;
+    std::vector<size_t> off_items;  // per launch
+    char *dev = nullptr;            // device copy of the blob (null until uploaded)
+    bool owns = false;              // dev was allocated by the library
     std::vector<Launch> launches;
-    std::vector<int32_t *> items;
 
     ~fht_batch_s()
     {
+        if (!owns || !dev) return;
         int cur = 0;
         const bool have = hipGetDevice(&cur) == hipSuccess;
         if (device >= 0) (void)hipSetDevice(device);
-        if (hdrs) (void)hipFree(hdrs);
-        if (ops) (void)hipFree(ops);
-        if (jobs) (void)hipFree(jobs);
-        for (int32_t *p : items)
-            if (p) (void)hipFree(p);
+        (void)hipFree(dev);
         if (have) (void)hipSetDevice(cur);
     }
 };
@@ -267,14 +277,129 @@ fht_status batch_one(fht_batch batch, size_t l, void *d_ws, void *stream)
     const Launch &L = batch->launches[l];
     fht::PassArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.items = reinterpret_cast<const int4 *>(batch->items[l]);
-    a.hdrs = batch->hdrs;
-    a.ops = reinterpret_cast<const int4 *>(batch->ops);
-    a.jobs = batch->jobs;
+    a.items = reinterpret_cast<const int4 *>(batch->dev + batch->off_items[l]);
+    a.hdrs = reinterpret_cast<const int32_t *>(batch->dev + batch->off_hdrs);
+    a.ops = reinterpret_cast<const int4 *>(batch->dev + batch->off_ops);
+    a.jobs = reinterpret_cast<const JobDesc *>(batch->dev + batch->off_jobs);
     a.ws = static_cast<char *>(d_ws);
     const int nitems = static_cast<int>(L.items.size() / 4);
     return hip_status(fht::launch_pass(L.combo, a, nitems, L.lds_bytes, L.threads,
                                        static_cast<hipStream_t>(stream)));
+}
+
+// Fault injection (fht_debug_fail_next): the next `g_fail_count` enqueue calls
+// return `g_fail_code` without enqueuing anything.
+std::atomic<int> g_fail_count{0};
+std::atomic<int> g_fail_code{0};
+
+bool injected_failure(fht_status *st)
+{
+    int c = g_fail_count.load();
+    while (c > 0) {
+        if (g_fail_count.compare_exchange_weak(c, c - 1)) {
+            *st = static_cast<fht_status>(g_fail_code.load());
+            return true;
+        }
+    }
+    return false;
+}
+
+// Host half of batch creation: the batch's launches and table blob.
+fht_status batch_prepare(fht_batch_s *b, const fht_plan *plans, int32_t n,
+                         const void *const *d_imgs, void *const *d_outs)
+{
+    // Distinct plans share one copy of their tables.
+    std::vector<fht_plan> uniq;
+    std::vector<int> hdr_base;
+    std::vector<int32_t> hdrs, ops;
+    auto table_of = [&](fht_plan p) {
+        for (size_t u = 0; u < uniq.size(); ++u)
+            if (uniq[u] == p) return static_cast<int>(u);
+        uniq.push_back(p);
+        hdr_base.push_back(static_cast<int>(hdrs.size() / fht::kHdrInts));
+        const int op_base = static_cast<int>(ops.size() / 4);
+        for (size_t i = 0; i < p->hdrs.size(); i += fht::kHdrInts) {
+            hdrs.insert(hdrs.end(), p->hdrs.begin() + i, p->hdrs.begin() + i + fht::kHdrInts);
+            hdrs[hdrs.size() - fht::kHdrInts] += op_base;
+        }
+        ops.insert(ops.end(), p->ops.begin(), p->ops.end());
+        return static_cast<int>(uniq.size() - 1);
+    };
+    // Batch launches keyed by (level, combination), in level order.
+    std::map<std::pair<int, int>, size_t> key;
+    std::vector<JobDesc> jobs;
+    size_t ws = 0;
+    for (int i = 0; i < n; ++i) {
+        const fht_plan p = plans[i];
+        const int u = table_of(p);
+        const size_t ws_base = ws;
+        ws += align_up(p->ws_bytes, 256);
+        for (const Launch &L : p->launches) {
+            const auto k = std::make_pair(L.level, static_cast<int>(L.combo));
+            auto found = key.find(k);
+            if (found == key.end()) {
+                found = key.emplace(k, b->launches.size()).first;
+                b->launches.emplace_back();
+                b->launches.back().level = L.level;
+                b->launches.back().combo = L.combo;
+                b->launches.back().threads = L.threads;
+            }
+            Launch &B = b->launches[found->second];
+            std::vector<int> slot;
+            for (int q : L.jobs_q) {
+                slot.push_back(static_cast<int>(jobs.size()));
+                jobs.push_back(p->job(q, L.level, d_imgs[i], d_outs[i], nullptr, ws_base));
+            }
+            for (size_t k4 = 0; k4 < L.items.size(); k4 += 4) {
+                B.items.push_back(L.items[k4] + hdr_base[u]);
+                B.items.push_back(slot[L.items[k4 + 1]]);
+                B.items.push_back(L.items[k4 + 2]);
+                B.items.push_back(0);
+            }
+            B.lds_bytes = std::max(B.lds_bytes, L.lds_bytes);
+        }
+    }
+    std::stable_sort(b->launches.begin(), b->launches.end(),
+                     [](const Launch &x, const Launch &y) { return x.level < y.level; });
+    b->ws_bytes = ws;
+
+    size_t off = 0;
+    auto place = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes, 256);
+        return at;
+    };
+    b->off_jobs = place(jobs.size() * sizeof(JobDesc));
+    b->off_hdrs = place(hdrs.size() * sizeof(int32_t));
+    b->off_ops = place(ops.size() * sizeof(int32_t));
+    for (const Launch &L : b->launches) b->off_items.push_back(place(L.items.size() * sizeof(int32_t)));
+    b->blob.assign(std::max<size_t>(off, 256), 0);
+    auto put = [&](size_t at, const void *src, size_t bytes) {
+        if (bytes) std::memcpy(b->blob.data() + at, src, bytes);
+    };
+    put(b->off_jobs, jobs.data(), jobs.size() * sizeof(JobDesc));
+    put(b->off_hdrs, hdrs.data(), hdrs.size() * sizeof(int32_t));
+    put(b->off_ops, ops.data(), ops.size() * sizeof(int32_t));
+    for (size_t l = 0; l < b->launches.size(); ++l)
+        put(b->off_items[l], b->launches[l].items.data(),
+            b->launches[l].items.size() * sizeof(int32_t));
+    return FHT_OK;
+}
+
+fht_status batch_checks(const fht_plan *plans, int32_t n, const void *const *d_imgs,
+                        void *const *d_outs)
+{
+    if (!plans || !d_imgs || !d_outs || n < 1) return FHT_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if (!plans[i] || !d_imgs[i] || !d_outs[i]) return FHT_EINVAL;
+    for (int i = 1; i < n; ++i)
+        if (plans[i]->dtype != plans[0]->dtype || plans[i]->split != plans[0]->split)
+            return FHT_EDTYPE;
+    for (int i = 1; i < n; ++i)
+        if (plans[i]->threads != plans[0]->threads ||
+            plans[i]->threads_first != plans[0]->threads_first)
+            return FHT_EINVAL;
+    return FHT_OK;
 }
 
 }  // namespace
@@ -351,6 +476,23 @@ fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, fht_dtype 
         }
         p->out_elems = off;
         p->ws_bytes = ws;
+        // Adjoint steps and their ping-pong buffers (float plans).
+        if (dtype != FHT_U8) {
+            for (int v = 0; v < 2; ++v)
+                if (quadrant_mask & (3u << (2 * v)))
+                    p->adj[v] = fht::plan_adjoint_axis(v == 0 ? rows : cols, static_cast<int>(split));
+            size_t aws = 0;
+            for (int q = 0; q < 4; ++q) {
+                if (!(quadrant_mask & (1u << q))) continue;
+                const fht::AdjointAxis &ax = p->adj[q >> 1];
+                const size_t wh = static_cast<size_t>(rows) * cols;
+                for (int b = 0; b < std::min(ax.levels, 2); ++b) {
+                    p->adj_ws_off[q][b] = aws;
+                    aws += align_up(wh * eb, 256);
+                }
+            }
+            p->adj_ws_bytes = aws;
+        }
         // Concatenate the program tables of both views.
         for (int v = 0; v < 2; ++v) {
             for (const fht::Pass &ps : p->axis[v].passes) {
@@ -471,6 +613,7 @@ fht_status fht_forward(fht_plan plan, const void *d_img, void *d_out, void *d_ws
 {
     const DevTables *t = nullptr;
     fht_status st = forward_checks(plan, d_img, d_out, d_ws, &t);
+    if (st == FHT_OK && injected_failure(&st)) return st;
     for (size_t l = 0; st == FHT_OK && l < plan->launches.size(); ++l)
         st = forward_one(plan, t, l, d_img, d_out, d_ws, stream);
     return st;
@@ -483,7 +626,44 @@ fht_status fht_forward_launch(fht_plan plan, int32_t launch, const void *d_img, 
     fht_status st = forward_checks(plan, d_img, d_out, d_ws, &t);
     if (st != FHT_OK) return st;
     if (launch < 0 || launch >= static_cast<int32_t>(plan->launches.size())) return FHT_EINVAL;
+    if (injected_failure(&st)) return st;
     return forward_one(plan, t, static_cast<size_t>(launch), d_img, d_out, d_ws, stream);
+}
+
+fht_status fht_batch_prepare(fht_batch *out, const fht_plan *plans, int32_t n,
+                             const void *const *d_imgs, void *const *d_outs)
+{
+    if (!out) return FHT_EINVAL;
+    *out = nullptr;
+    const fht_status st = batch_checks(plans, n, d_imgs, d_outs);
+    if (st != FHT_OK) return st;
+    fht_batch_s *b = new (std::nothrow) fht_batch_s;
+    if (!b) return FHT_ENOMEM;
+    b->dtype = plans[0]->dtype;
+    try {
+        batch_prepare(b, plans, n, d_imgs, d_outs);
+    } catch (const std::bad_alloc &) {
+        delete b;
+        return FHT_ENOMEM;
+    }
+    *out = b;
+    return FHT_OK;
+}
+
+size_t fht_batch_tables_bytes(fht_batch batch) { return batch ? batch->blob.size() : 0; }
+
+fht_status fht_batch_upload(fht_batch batch, void *d_tables, size_t bytes, void *stream)
+{
+    if (!batch || !d_tables || bytes < batch->blob.size() || batch->owns) return FHT_EINVAL;
+    fht_status st = FHT_OK;
+    if (injected_failure(&st)) return st;
+    hipError_t e = hipGetDevice(&batch->device);
+    if (e != hipSuccess) return hip_status(e);
+    e = hipMemcpyAsync(d_tables, batch->blob.data(), batch->blob.size(), hipMemcpyHostToDevice,
+                       static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_status(e);
+    batch->dev = static_cast<char *>(d_tables);
+    return FHT_OK;
 }
 
 fht_status fht_batch_create(fht_batch *out, const fht_plan *plans, int32_t n,
@@ -491,97 +671,22 @@ fht_status fht_batch_create(fht_batch *out, const fht_plan *plans, int32_t n,
 {
     if (!out) return FHT_EINVAL;
     *out = nullptr;
-    if (!plans || !d_imgs || !d_outs || n < 1) return FHT_EINVAL;
-    for (int i = 0; i < n; ++i)
-        if (!plans[i] || !d_imgs[i] || !d_outs[i]) return FHT_EINVAL;
-    for (int i = 1; i < n; ++i)
-        if (plans[i]->dtype != plans[0]->dtype || plans[i]->split != plans[0]->split)
-            return FHT_EDTYPE;
-    for (int i = 1; i < n; ++i)
-        if (plans[i]->threads != plans[0]->threads ||
-            plans[i]->threads_first != plans[0]->threads_first)
-            return FHT_EINVAL;
+    fht_status st = batch_checks(plans, n, d_imgs, d_outs);
+    if (st != FHT_OK) return st;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return FHT_ENODEV;
-
-    fht_batch_s *b = new (std::nothrow) fht_batch_s;
-    if (!b) return FHT_ENOMEM;
-    b->dtype = plans[0]->dtype;
+    fht_batch b = nullptr;
+    st = fht_batch_prepare(&b, plans, n, d_imgs, d_outs);
+    if (st != FHT_OK) return st;
     hipError_t e = hipGetDevice(&b->device);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&b->dev), b->blob.size());
+    if (e == hipSuccess) {
+        b->owns = true;
+        e = hipMemcpy(b->dev, b->blob.data(), b->blob.size(), hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         delete b;
         return hip_status(e);
-    }
-    try {
-        // Distinct plans share one copy of their tables.
-        std::vector<fht_plan> uniq;
-        std::vector<int> hdr_base;
-        std::vector<int32_t> hdrs, ops;
-        auto table_of = [&](fht_plan p) {
-            for (size_t u = 0; u < uniq.size(); ++u)
-                if (uniq[u] == p) return static_cast<int>(u);
-            uniq.push_back(p);
-            hdr_base.push_back(static_cast<int>(hdrs.size() / fht::kHdrInts));
-            const int op_base = static_cast<int>(ops.size() / 4);
-            for (size_t i = 0; i < p->hdrs.size(); i += fht::kHdrInts) {
-                hdrs.insert(hdrs.end(), p->hdrs.begin() + i, p->hdrs.begin() + i + fht::kHdrInts);
-                hdrs[hdrs.size() - fht::kHdrInts] += op_base;
-            }
-            ops.insert(ops.end(), p->ops.begin(), p->ops.end());
-            return static_cast<int>(uniq.size() - 1);
-        };
-        // Batch launches keyed by (level, combination), in level order.
-        std::map<std::pair<int, int>, size_t> key;
-        std::vector<JobDesc> jobs;
-        size_t ws = 0;
-        for (int i = 0; i < n; ++i) {
-            const fht_plan p = plans[i];
-            const int u = table_of(p);
-            const size_t ws_base = ws;
-            ws += align_up(p->ws_bytes, 256);
-            for (const Launch &L : p->launches) {
-                const auto k = std::make_pair(L.level, static_cast<int>(L.combo));
-                auto found = key.find(k);
-                if (found == key.end()) {
-                    found = key.emplace(k, b->launches.size()).first;
-                    b->launches.emplace_back();
-                    b->launches.back().level = L.level;
-                    b->launches.back().combo = L.combo;
-                    b->launches.back().threads = L.threads;
-                }
-                Launch &B = b->launches[found->second];
-                std::vector<int> slot;
-                for (int q : L.jobs_q) {
-                    slot.push_back(static_cast<int>(jobs.size()));
-                    jobs.push_back(p->job(q, L.level, d_imgs[i], d_outs[i], nullptr, ws_base));
-                }
-                for (size_t k4 = 0; k4 < L.items.size(); k4 += 4) {
-                    B.items.push_back(L.items[k4] + hdr_base[u]);
-                    B.items.push_back(slot[L.items[k4 + 1]]);
-                    B.items.push_back(L.items[k4 + 2]);
-                    B.items.push_back(0);
-                }
-                B.lds_bytes = std::max(B.lds_bytes, L.lds_bytes);
-            }
-        }
-        std::stable_sort(b->launches.begin(), b->launches.end(),
-                         [](const Launch &x, const Launch &y) { return x.level < y.level; });
-        b->ws_bytes = ws;
-        e = upload(hdrs, &b->hdrs);
-        if (e == hipSuccess) e = upload(ops, &b->ops);
-        if (e == hipSuccess) e = upload(jobs, &b->jobs);
-        for (size_t l = 0; e == hipSuccess && l < b->launches.size(); ++l) {
-            int32_t *ptr = nullptr;
-            e = upload(b->launches[l].items, &ptr);
-            b->items.push_back(ptr);
-        }
-        if (e != hipSuccess) {
-            delete b;
-            return hip_status(e);
-        }
-    } catch (const std::bad_alloc &) {
-        delete b;
-        return FHT_ENOMEM;
     }
     *out = b;
     return FHT_OK;
@@ -596,9 +701,10 @@ int32_t fht_batch_num_launches(fht_batch batch)
 
 fht_status fht_batch_run(fht_batch batch, void *d_ws, void *stream)
 {
-    if (!batch) return FHT_EINVAL;
+    if (!batch || !batch->dev) return FHT_EINVAL;
     if (batch->ws_bytes && !d_ws) return FHT_EINVAL;
     fht_status st = FHT_OK;
+    if (injected_failure(&st)) return st;
     for (size_t l = 0; st == FHT_OK && l < batch->launches.size(); ++l)
         st = batch_one(batch, l, d_ws, stream);
     return st;
@@ -606,13 +712,140 @@ fht_status fht_batch_run(fht_batch batch, void *d_ws, void *stream)
 
 fht_status fht_batch_run_launch(fht_batch batch, int32_t launch, void *d_ws, void *stream)
 {
-    if (!batch) return FHT_EINVAL;
+    if (!batch || !batch->dev) return FHT_EINVAL;
     if (batch->ws_bytes && !d_ws) return FHT_EINVAL;
     if (launch < 0 || launch >= static_cast<int32_t>(batch->launches.size())) return FHT_EINVAL;
+    fht_status st = FHT_OK;
+    if (injected_failure(&st)) return st;
     return batch_one(batch, static_cast<size_t>(launch), d_ws, stream);
 }
 
 void fht_batch_destroy(fht_batch batch) { delete batch; }
+
+size_t fht_plan_adjoint_workspace_bytes(fht_plan plan) { return plan ? plan->adj_ws_bytes : 0; }
+
+fht_status fht_plan_adjoint_tasks(fht_plan plan, int32_t v, const int32_t **tasks,
+                                  int32_t *levels, int32_t *lanes)
+{
+    if (!plan || v < 0 || v > 1 || !(plan->qmask & (3u << (2 * v)))) return FHT_EINVAL;
+    if (plan->dtype == FHT_U8) return FHT_EDTYPE;
+    const fht::AdjointAxis &ax = plan->adj[v];
+    if (tasks) *tasks = ax.tasks.data();
+    if (levels) *levels = ax.levels;
+    if (lanes) *lanes = ax.W;
+    return FHT_OK;
+}
+
+fht_status fht_adjoint(fht_plan plan, const void *d_gout, void *d_gimg, void *d_ws, void *stream)
+{
+    if (!plan || !d_gout || !d_gimg) return FHT_EINVAL;
+    if (plan->dtype == FHT_U8) return FHT_EDTYPE;
+    if (plan->adj_ws_bytes && !d_ws) return FHT_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return FHT_ENODEV;
+    const DevTables *t = nullptr;
+    fht_status st = plan->tables(&t);
+    if (st != FHT_OK) return st;
+    if (injected_failure(&st)) return st;
+    const fht::Real real = plan->dtype == FHT_F64 ? fht::Real::F64 : fht::Real::F32;
+    const size_t eb = acc_bytes(plan->dtype);
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    char *ws = static_cast<char *>(d_ws);
+    const char *gout = static_cast<const char *>(d_gout);
+    int max_levels = 0;
+    for (int q = 0; q < 4; ++q)
+        if (plan->qmask & (1u << q)) max_levels = std::max(max_levels, plan->adj[q >> 1].levels);
+    for (int k = 0; k < max_levels; ++k) {
+        fht::AdjArgs a;
+        std::memset(&a, 0, sizeof(a));
+        int nj = 0, max_w = 0;
+        for (int q = 0; q < 4; ++q) {
+            if (!(plan->qmask & (1u << q))) continue;
+            const fht::AdjointAxis &ax = plan->adj[q >> 1];
+            if (ax.levels <= k) continue;
+            fht::AdjJob &j = a.job[nj++];
+            j.src = k == 0 ? static_cast<const void *>(gout + plan->out_off[q] * eb)
+                           : static_cast<const void *>(ws + plan->adj_ws_off[q][(k - 1) & 1]);
+            j.dst = ws + plan->adj_ws_off[q][k & 1];
+            j.tasks = reinterpret_cast<const int4 *>(t->adj[q >> 1] +
+                                                     static_cast<size_t>(k) * ax.W * 4);
+            j.W = ax.W;
+            j.H = (q >> 1) ? plan->R : plan->C;
+            j.mirror_in = (k == 0 && (q & 1)) ? 1 : 0;
+            max_w = std::max(max_w, ax.W);
+        }
+        const hipError_t e = fht::launch_adjoint_step(real, a, nj, max_w, hs);
+        if (e != hipSuccess) return hip_status(e);
+    }
+    fht::CombineArgs c;
+    std::memset(&c, 0, sizeof(c));
+    c.R = plan->R;
+    c.C = plan->C;
+    c.dst = d_gimg;
+    for (int q = 0; q < 4; ++q) {
+        if (!(plan->qmask & (1u << q))) continue;
+        const int L = plan->adj[q >> 1].levels;
+        // after the steps a negative-slope quadrant is in the mirrored frame
+        c.src[q] = L > 0 ? static_cast<const void *>(ws + plan->adj_ws_off[q][(L - 1) & 1])
+                         : static_cast<const void *>(gout + plan->out_off[q] * eb);
+        c.mirror[q] = (L > 0 && (q & 1)) ? 1 : 0;
+    }
+    return hip_status(fht::launch_adjoint_combine(real, c, hs));
+}
+
+size_t fht_peaks_workspace_bytes(int32_t capacity)
+{
+    if (capacity < 1) return 0;
+    return 256 + static_cast<size_t>(capacity) * sizeof(uint64_t);
+}
+
+fht_status fht_peaks(fht_plan plan, const void *d_out, int32_t k, int32_t radius,
+                     double min_value, int32_t capacity, void *d_ws, fht_peak *d_peaks,
+                     int32_t *d_found, void *stream)
+{
+    if (!plan || !d_out || !d_ws || !d_peaks || !d_found) return FHT_EINVAL;
+    if (k < 1 || k > 4096 || radius < 0 || radius > 64 || capacity < k || capacity > (1 << 26))
+        return FHT_EINVAL;
+    if (plan->out_elems >= 0xffffffffull) return FHT_EINVAL;
+    static_assert(sizeof(fht_peak) == sizeof(fht::PeakOut), "peak layout");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return FHT_ENODEV;
+    fht_status st = FHT_OK;
+    if (injected_failure(&st)) return st;
+    fht::PeakArgs a;
+    std::memset(&a, 0, sizeof(a));
+    const size_t eb = acc_bytes(plan->dtype);
+    int max_elems = 0;
+    for (int q = 0; q < 4; ++q) {
+        if (!(plan->qmask & (1u << q))) continue;
+        const fht::AxisPlan &ax = plan->axis[q >> 1];
+        const int j = a.nq++;
+        a.src[j] = static_cast<const char *>(d_out) + plan->out_off[q] * eb;
+        a.W[j] = ax.W;
+        a.H[j] = ax.H;
+        a.base[j] = plan->out_off[q];
+        a.quadrant[j] = q;
+        max_elems = std::max(max_elems, ax.W * ax.H);
+    }
+    a.radius = radius;
+    a.min_value = min_value;
+    a.k = k;
+    a.capacity = capacity;
+    a.counter = static_cast<uint32_t *>(d_ws);
+    a.keys = reinterpret_cast<uint64_t *>(static_cast<char *>(d_ws) + 256);
+    a.out = reinterpret_cast<fht::PeakOut *>(d_peaks);
+    a.n_found = d_found;
+    const fht::PeakElem elem = plan->dtype == FHT_U8    ? fht::PeakElem::I32
+                               : plan->dtype == FHT_F32 ? fht::PeakElem::F32
+                                                        : fht::PeakElem::F64;
+    return hip_status(fht::launch_peaks(elem, a, max_elems, static_cast<hipStream_t>(stream)));
+}
+
+void fht_debug_fail_next(fht_status code, int32_t count)
+{
+    g_fail_code.store(static_cast<int>(code));
+    g_fail_count.store(count > 0 && code != FHT_OK ? count : 0);
+}
 
 int32_t fht_plan_num_passes(fht_plan plan, int32_t v)
 {

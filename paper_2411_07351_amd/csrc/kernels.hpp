@@ -58,4 +58,61 @@ enum class Combo {
 hipError_t launch_pass(Combo combo, const PassArgs &args, int n_items, int lds_bytes, int threads,
                        hipStream_t stream);
 
+// Adjoint (back-projection).  One gather step of one quadrant: rows of the
+// gradient of one frontier to those of the next frontier down (see
+// fht::AdjointAxis for the task format).
+struct AdjJob {
+    const void *src;     // [W][H] gradient rows in (the output gradient at step 0)
+    void *dst;           // [W][H] gradient rows out
+    const int4 *tasks;   // W tasks {p0, n, r0, right}
+    int32_t W, H;
+    int32_t mirror_in;   // read src at mirrored positions (step 0 of V-/H-)
+    int32_t pad;
+};
+
+struct AdjArgs {
+    AdjJob job[kInlineJobs];
+};
+
+// Sum of the quadrants' lane gradients into the image gradient (R x C):
+// quadrants 0/1 have lanes = rows, 2/3 lanes = columns; `mirror` reads the
+// positions at (H - y) mod H.
+struct CombineArgs {
+    const void *src[kInlineJobs];  // null: quadrant absent
+    int32_t mirror[kInlineJobs];
+    int32_t R, C;
+    void *dst;
+};
+
+enum class Real { F32, F64 };
+
+// Peak finding over the quadrant outputs of one image.
+struct PeakOut {
+    float value;
+    int32_t quadrant, t, s;
+};
+
+struct PeakArgs {
+    const void *src[kInlineJobs];  // quadrant outputs [W][H], present ones first
+    int32_t W[kInlineJobs], H[kInlineJobs];
+    uint64_t base[kInlineJobs];    // flat output index of each quadrant's first element
+    int32_t quadrant[kInlineJobs];
+    int32_t nq;
+    int32_t radius;
+    double min_value;
+    int32_t k, capacity;
+    uint32_t *counter;             // workspace: candidate count
+    uint64_t *keys;                // workspace: candidate keys (value bits << 32 | ~index)
+    PeakOut *out;                  // k peaks, strongest first
+    int32_t *n_found;              // [0] peaks written, [1] candidates found
+};
+
+enum class PeakElem { I32, F32, F64 };
+
+hipError_t launch_peaks(PeakElem elem, const PeakArgs &args, int max_elems, hipStream_t stream);
+
+hipError_t launch_adjoint_step(Real real, const AdjArgs &args, int n_jobs, int max_w,
+                               hipStream_t stream);
+hipError_t launch_adjoint_combine(Real real, const CombineArgs &args, hipStream_t stream);
+
 }  // namespace fht

@@ -372,4 +372,52 @@ bool plan_axis(int W, int H, int split, const ElemRule &rule, const Schedule &sc
     return true;
 }
 
+// Adjoint steps.  The forward merge of a node of width w into children of
+// widths w0, w1 is J[t] = J0[t0(t)] + Rotate(J1[t1(t)], t - t1(t)); its adjoint
+// gives left-child row u the sum of the parent rows t with t0(t) = u, and
+// right-child row u the sum of the parent rows t with t1(t) = u, each rotated
+// back by t - u.  Both preimages are contiguous ranges of t because t0 and t1
+// are non-decreasing in t with steps of at most one, and neither is empty.
+AdjointAxis plan_adjoint_axis(int W, int split)
+{
+    AdjointAxis ax;
+    ax.W = W;
+    const Tree tr = make_tree(W, split);
+    ax.levels = tr.nodes[0].height;
+    ax.tasks.assign(static_cast<size_t>(ax.levels) * W * 4, 0);
+    for (int k = 0; k < ax.levels; ++k) {
+        const int level = ax.levels - k;
+        int32_t *task = ax.tasks.data() + static_cast<size_t>(k) * W * 4;
+        std::vector<int> nodes;
+        collect_frontier(tr, 0, level, &nodes);
+        for (int ni : nodes) {
+            const Node &n = tr.nodes[ni];
+            if (n.height < level) {  // also in the next frontier: passed through
+                for (int u = 0; u < n.w; ++u) {
+                    int32_t *e = task + 4 * (n.a + u);
+                    e[0] = n.a + u; e[1] = 1; e[2] = 0; e[3] = 0;
+                }
+                continue;
+            }
+            const int w = n.w, w0 = n.w0, w1 = w - w0;
+            // preimages, walking t upwards
+            int t = 0;
+            for (int u = 0; u < w0; ++u) {
+                const int lo = t;
+                while (t < w && round_half_even(int64_t(t) * (w0 - 1), w - 1) == u) ++t;
+                int32_t *e = task + 4 * (n.a + u);
+                e[0] = n.a + lo; e[1] = t - lo; e[2] = 0; e[3] = 0;
+            }
+            t = 0;
+            for (int u = 0; u < w1; ++u) {
+                const int lo = t;
+                while (t < w && round_half_even(int64_t(t) * (w1 - 1), w - 1) == u) ++t;
+                int32_t *e = task + 4 * (n.a + w0 + u);
+                e[0] = n.a + lo; e[1] = t - lo; e[2] = lo - u; e[3] = 1;
+            }
+        }
+    }
+    return ax;
+}
+
 }  // namespace fht

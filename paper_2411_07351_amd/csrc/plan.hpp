@@ -87,4 +87,17 @@ struct ElemRule {
 bool plan_axis(int W, int H, int split, const ElemRule &rule, const Schedule &sched,
                AxisPlan *out, std::string *err);
 
+// Gather steps of the adjoint (back-projection) of Alg. 1, top down.  Step k
+// takes the gradients of the frontier of level L - k (L = root height) to
+// those of level L - k - 1; in every step, output row x is
+//   g_out[x][s] = sum_{j < n} g_in[p0 + j][(s - (right ? r0 + j : 0)) mod H]
+// with tasks[(k W + x) 4 ..] = {p0, n, r0, right}.  Rows of a node sit at its
+// lane range, as in the forward direction.
+struct AdjointAxis {
+    int W = 0, levels = 0;
+    std::vector<int32_t> tasks;  // levels x W x 4
+};
+
+AdjointAxis plan_adjoint_axis(int W, int split);
+
 }  // namespace fht

@@ -319,3 +319,75 @@ def test_pins_reject_planted_mistakes(monkeypatch):
     assert O.pattern(5, 1, O.SPLIT_S) != [0, 0, 1, 1, 1]
     monkeypatch.undo()
     O._patterns_cached.cache_clear()
+
+
+# --------------------------------------------------------------------- adjoint
+
+ADJ_SHAPES = [(13, 11), (11, 13), (7, 5), (16, 3), (1, 5), (5, 1), (17, 9)]
+
+
+@pytest.mark.parametrize("split", SPLITS)
+@pytest.mark.parametrize("shape", ADJ_SHAPES)
+def test_adjoint_dot_product_identity(split, shape):
+    # <F A, G> = <A, F^T G> for the forward oracle F (integer data: exact)
+    rng = np.random.default_rng(31 + shape[0] * 7 + shape[1])
+    A = rng.integers(-9, 10, size=shape)
+    G = rng.integers(-9, 10, size=shape)
+    for sigma in (1, -1):
+        lhs = int((O.hough_lanes(A, split, sigma) * G).sum())
+        rhs = float((A * O.adjoint_lanes(G, split, sigma)).sum())
+        assert rhs == lhs
+
+
+@pytest.mark.parametrize("split", SPLITS)
+@pytest.mark.parametrize("shape", [(13, 11), (11, 13), (7, 5), (16, 3)])
+def test_adjoint_is_the_explicit_transpose(split, shape):
+    rng = np.random.default_rng(5)
+    W, H = shape
+    G = rng.standard_normal(shape)
+    for sigma in (1, -1):
+        M = O.explicit_matrix(W, H, split, sigma)
+        np.testing.assert_allclose(O.adjoint_lanes(G, split, sigma).ravel(), M.T @ G.ravel(),
+                                   rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("split", SPLITS)
+def test_adjoint_of_one_line_is_its_pattern(split):
+    # the gradient of a single output J[t][s] marks the pixels of that line:
+    # one per lane, at (s + pat_t(x)) mod H (Alg. 2, Sec. 3)
+    W, H = 9, 7
+    for t in range(W):
+        G = np.zeros((W, H))
+        G[t, 3] = 1.0
+        gA = O.adjoint_lanes(G, split)
+        assert gA.sum() == W and (gA.sum(axis=1) == 1).all()
+        pat = O.pattern(W, t, split)
+        for x in range(W):
+            assert gA[x, (3 + pat[x]) % H] == 1.0
+
+
+@pytest.mark.parametrize("split", SPLITS)
+def test_adjoint4_dot_product_identity(split):
+    rng = np.random.default_rng(77)
+    img = rng.integers(-5, 6, size=(9, 6))
+    outs = O.hough4(img, split)
+    Gs = {q: rng.integers(-5, 6, size=o.shape) for q, o in enumerate(outs)}
+    lhs = sum(int((o * Gs[q]).sum()) for q, o in enumerate(outs))
+    assert float((img * O.adjoint4(Gs, split, img.shape)).sum()) == lhs
+    # a subset of quadrants contributes only its own terms
+    sub = {0: Gs[0], 3: Gs[3]}
+    lhs = int((outs[0] * Gs[0]).sum() + (outs[3] * Gs[3]).sum())
+    assert float((img * O.adjoint4(sub, split, img.shape)).sum()) == lhs
+
+
+def test_adjoint_pins_reject_a_sign_mistake():
+    # the dot-product pin catches an adjoint that walks the pattern the wrong way
+    rng = np.random.default_rng(3)
+    A = rng.integers(-9, 10, size=(7, 5))
+    G = rng.integers(-9, 10, size=(7, 5))
+    P = O.patterns(7, O.SPLIT_S)
+    wrong = np.zeros((7, 5))
+    for x in range(7):
+        for t in range(7):
+            wrong[x] += G[t][(np.arange(5) + P[t, x]) % 5]
+    assert float((A * wrong).sum()) != int((O.hough_lanes(A, O.SPLIT_S) * G).sum())
