@@ -130,6 +130,14 @@ int32_t fht_plan_num_launches(fht_plan plan);
 fht_status fht_plan_launch_info(fht_plan plan, int32_t launch, int32_t *level,
                                 int64_t *bytes_in, int64_t *bytes_out, int32_t *n_items);
 
+/* Additions of the plan's forward transform, summed over its quadrants:
+ * *adds_tree is the count of Alg. 1 (every non-leaf node of width w of the
+ * order tree adds w rows of H positions: Theorem 1's f(n) for n x n);
+ * *adds_executed is what the fused kernels add, whole 64-position chunks of
+ * every merge including the halo positions of their tiles.  Host only; either
+ * pointer may be NULL.  Errors: FHT_EINVAL. */
+fht_status fht_plan_work(fht_plan plan, int64_t *adds_tree, int64_t *adds_executed);
+
 /* Copy the plan's tables to the current HIP device (idempotent).  Needed only
  * before capturing fht_forward into a HIP graph.  Errors: FHT_ENODEV, FHT_ENOMEM,
  * FHT_EHIP. */

@@ -722,6 +722,32 @@ fht_status fht_batch_run_launch(fht_batch batch, int32_t launch, void *d_ws, voi
 
 void fht_batch_destroy(fht_batch batch) { delete batch; }
 
+fht_status fht_plan_work(fht_plan plan, int64_t *adds_tree, int64_t *adds_executed)
+{
+    if (!plan) return FHT_EINVAL;
+    int64_t tree = 0, done = 0;
+    for (int q = 0; q < 4; ++q) {
+        if (!(plan->qmask & (1u << q))) continue;
+        const fht::AxisPlan &ax = plan->axis[q >> 1];
+        // Theorem 1's count: every non-leaf node of width w merges w rows of H
+        const fht::Tree tr = fht::make_tree(ax.W, ax.split);
+        for (const fht::Node &n : tr.nodes)
+            if (n.w > 1) tree += static_cast<int64_t>(n.w) * ax.H;
+        // what the kernels add: whole 64-position chunks of every merge entry
+        for (const fht::Pass &ps : ax.passes) {
+            for (size_t i = 0; i < ps.items.size(); i += 4) {
+                const int32_t *h = ps.hdrs.data() + static_cast<size_t>(ps.items[i]) * fht::kHdrInts;
+                int64_t merges = 0;
+                for (int k = 0; k < h[3]; ++k) merges += h[8 + k];
+                done += merges * h[fht::kHdrChunks] * fht::kChunk;
+            }
+        }
+    }
+    if (adds_tree) *adds_tree = tree;
+    if (adds_executed) *adds_executed = done;
+    return FHT_OK;
+}
+
 size_t fht_plan_adjoint_workspace_bytes(fht_plan plan) { return plan ? plan->adj_ws_bytes : 0; }
 
 fht_status fht_plan_adjoint_tasks(fht_plan plan, int32_t v, const int32_t **tasks,

@@ -90,3 +90,17 @@ def test_invalid_arguments():
         F.fht_plan_create(4, 4, F.FHT_U8, 2, 15, None)
     with pytest.raises(F.FhtError):
         F.fht_plan_create(4, 4, F.FHT_U8, 0, 15, F.fht_schedule(s_tile=96))
+
+
+@pytest.mark.parametrize("split", ["S", "T"])
+def test_plan_addition_count_equals_theorem1_count(split):
+    # the library's order tree adds exactly what the oracle counts for Alg. 1
+    # (Sec. 4); the fused kernels add at least that many
+    sp = 0 if split == "S" else 1
+    for R, C in [(1, 1), (1, 9), (9, 1), (61, 47), (384, 257), (1021, 1021), (1024, 1024),
+                 (3, 3), (17, 17), (1451, 13), (4096, 5)]:
+        plan = F.Plan(R, C, "u8", split)  # keep it alive while its handle is used
+        w = F.fht_plan_work(plan.handle)
+        expect = 2 * O.additions(R, sp, C) + 2 * O.additions(C, sp, R)
+        assert w["adds_tree"] == expect, (R, C)
+        assert w["adds_executed"] >= expect
