@@ -277,10 +277,7 @@ def main():
     dom = int(np.argmax(launch_ms))
     dom_bytes = info[dom]["bytes_in"] + info[dom]["bytes_out"]
     achieved = dom_bytes / (launch_ms[dom] * 1e-3) / 1e9
-    kernels = ["fht_pass_kernel<256, unsigned char, unsigned short, unsigned short, true, false>",
-               "fht_pass_kernel<256, unsigned short, unsigned short, unsigned short, false, false>",
-               "fht_pass_kernel<256, unsigned short, int, int, false, false>"]
-    dom_kernel = kernels[dom] if nl == 3 and dom < 3 else f"launch {dom}"
+    dom_kernel = F.fht_plan_launch_kernel(plan.handle, dom)
     traffic = _traffic(dom_kernel)
 
     value = px_per_step * args.steps / plain_s / 1e6
@@ -317,6 +314,7 @@ def main():
             "avg_launch_us": round(launch_ms[dom] * 1e3, 2),
             "launch_avg_us": [round(m * 1e3, 2) for m in launch_ms],
             "launch_bytes": [i["bytes_in"] + i["bytes_out"] for i in info],
+            "launch_kernels": [F.fht_plan_launch_kernel(plan.handle, l) for l in range(nl)],
             "kernel_source_hash": kernel_source_hash(),
         },
     }

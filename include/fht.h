@@ -72,7 +72,7 @@ typedef struct fht_batch_s *fht_batch;
  *                 192 or 256); the pass takes the largest position tile that fits
  *   first_levels  tree levels fused in the first pass (1..6)
  *   max_levels    tree levels fused in each later pass (1..16)
- *   lds_budget    LDS bytes a work item may use (1024..65536)
+ *   lds_budget    LDS bytes a work item may use (1024..163840)
  *   t_tile        slope rows per work item in later passes, halved while the
  *                 pass does not fit the LDS budget (-1: start from 32)
  *   s_tile_first  widest row window of the first pass (64..256, multiple of 64)
@@ -137,6 +137,11 @@ fht_status fht_plan_launch_info(fht_plan plan, int32_t launch, int32_t *level,
  * every merge including the halo positions of their tiles.  Host only; either
  * pointer may be NULL.  Errors: FHT_EINVAL. */
 fht_status fht_plan_work(fht_plan plan, int64_t *adds_tree, int64_t *adds_executed);
+
+/* The signature of the kernel launch `launch` of fht_forward runs, as
+ * profilers print it (without its namespace and arguments), valid while the
+ * plan lives; NULL for a bad index. */
+const char *fht_plan_launch_kernel(fht_plan plan, int32_t launch);
 
 /* Copy the plan's tables to the current HIP device (idempotent).  Needed only
  * before capturing fht_forward into a HIP graph.  Errors: FHT_ENODEV, FHT_ENOMEM,

@@ -36,7 +36,7 @@ __all__ = [
     "fht_batch_prepare", "fht_batch_tables_bytes", "fht_batch_upload", "fht_debug_fail_next",
     "fht_plan_adjoint_workspace_bytes", "fht_plan_adjoint_tasks", "fht_adjoint",
     "HoughFunction", "hough_autograd", "fht_peaks_workspace_bytes", "fht_peaks", "PEAK_DTYPE",
-    "fht_plan_work",
+    "fht_plan_work", "fht_plan_launch_kernel",
 ]
 
 FHT_U8, FHT_F32, FHT_F64 = 0, 1, 2
@@ -55,7 +55,7 @@ EXPORTED = (
     "fht_batch_run_launch", "fht_batch_destroy", "fht_plan_num_passes", "fht_plan_pass_tables",
     "fht_batch_prepare", "fht_batch_tables_bytes", "fht_batch_upload", "fht_debug_fail_next",
     "fht_plan_adjoint_workspace_bytes", "fht_plan_adjoint_tasks", "fht_adjoint",
-    "fht_peaks_workspace_bytes", "fht_peaks", "fht_plan_work",
+    "fht_peaks_workspace_bytes", "fht_peaks", "fht_plan_work", "fht_plan_launch_kernel",
 )
 
 # struct fht_peak
@@ -94,6 +94,7 @@ _sig("fht_plan_num_launches", _i32, _vp)
 _sig("fht_plan_launch_info", _i32, _vp, _i32, _pi32, ctypes.POINTER(_i64),
      ctypes.POINTER(_i64), _pi32)
 _sig("fht_plan_work", _i32, _vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64))
+_sig("fht_plan_launch_kernel", ctypes.c_char_p, _vp, _i32)
 _sig("fht_plan_upload", _i32, _vp)
 _sig("fht_forward", _i32, _vp, _vp, _vp, _vp, _vp)
 _sig("fht_forward_launch", _i32, _vp, _i32, _vp, _vp, _vp, _vp)
@@ -178,6 +179,13 @@ def fht_plan_work(plan: int) -> dict:
     tree, done = _i64(), _i64()
     _check(_lib.fht_plan_work(plan, ctypes.byref(tree), ctypes.byref(done)), "fht_plan_work")
     return {"adds_tree": tree.value, "adds_executed": done.value}
+
+
+def fht_plan_launch_kernel(plan: int, launch: int) -> str:
+    name = _lib.fht_plan_launch_kernel(plan, launch)
+    if name is None:
+        raise FhtError(-1, "fht_plan_launch_kernel")
+    return name.decode()
 
 
 def fht_plan_upload(plan: int) -> None:

@@ -55,10 +55,17 @@ hipError_t upload(const std::vector<T> &host, T **dev)
 // uint8 images keep 16-bit sums while nodes are at most this wide.
 constexpr int kNarrowWidth = 257;
 
-// Element types of pass p of an axis plan (see fht::Combo).
-Combo pass_combo(fht_dtype dt, const fht::AxisPlan &ax, size_t p)
+// Element types of pass p of an axis plan (see fht::Combo); `pair` selects
+// the quadrant-pair form.
+Combo pass_combo(fht_dtype dt, const fht::AxisPlan &ax, size_t p, bool pair)
 {
     const bool final = p + 1 == ax.passes.size();
+    if (pair) {
+        if (p == 0) return final ? Combo::P_U8_FIRST_FINAL : Combo::P_U8_FIRST;
+        if (ax.passes[p].max_root_w <= kNarrowWidth)
+            return final ? Combo::P_U16_MID_FINAL : Combo::P_U16_MID;
+        return Combo::P_I32;
+    }
     if (dt == FHT_F32) return p == 0 ? Combo::F32_FIRST : Combo::F32_LATER;
     if (dt == FHT_F64) return p == 0 ? Combo::F64_FIRST : Combo::F64_LATER;
     const bool narrow_out = ax.passes[p].max_root_w <= kNarrowWidth;
@@ -69,6 +76,12 @@ Combo pass_combo(fht_dtype dt, const fht::AxisPlan &ax, size_t p)
     return final ? Combo::U16_U16_I32 : Combo::U16_U16_U16;
 }
 
+// A job slot of a plan launch: quadrant q, or the pair q, q + 1 of one lane view.
+struct JobRef {
+    int q = 0;
+    bool pair = false;
+};
+
 // One kernel launch: the work items of one level and one type combination.
 struct Launch {
     int level = 0;
@@ -76,8 +89,36 @@ struct Launch {
     int lds_bytes = 0;
     int threads = 256;
     std::vector<int32_t> items;  // {program, job slot, first position, 0}
-    std::vector<int> jobs_q;     // plan launches: quadrant of each job slot
+    std::vector<JobRef> jobs;    // plan launches: what each job slot runs
+    std::string kernel;          // plan launches: the kernel's template signature
 };
+
+// The signature of the kernel a launch runs, as profilers print it.
+std::string kernel_name(Combo c, int threads, bool table)
+{
+    const char *src = "int", *lds = "int", *dst = "int";
+    bool first = false, pair = false;
+    switch (c) {
+    case Combo::U8_U16_U16: src = "unsigned char"; lds = dst = "unsigned short"; first = true; break;
+    case Combo::U8_U16_I32: src = "unsigned char"; lds = "unsigned short"; first = true; break;
+    case Combo::U16_U16_U16: src = lds = dst = "unsigned short"; break;
+    case Combo::U16_U16_I32: src = lds = "unsigned short"; break;
+    case Combo::U16_I32_I32: src = "unsigned short"; break;
+    case Combo::I32_I32_I32: break;
+    case Combo::F32_FIRST: first = true; [[fallthrough]];
+    case Combo::F32_LATER: src = lds = dst = "float"; break;
+    case Combo::F64_FIRST: first = true; [[fallthrough]];
+    case Combo::F64_LATER: src = lds = dst = "double"; break;
+    case Combo::P_U8_FIRST: src = "unsigned char"; lds = dst = "unsigned int"; first = pair = true; break;
+    case Combo::P_U8_FIRST_FINAL: src = "unsigned char"; lds = "unsigned int"; first = pair = true; break;
+    case Combo::P_U16_MID: src = lds = dst = "unsigned int"; pair = true; break;
+    case Combo::P_U16_MID_FINAL: src = lds = "unsigned int"; pair = true; break;
+    case Combo::P_I32: src = "unsigned int"; lds = "HIP_vector_type<unsigned int, 2u>"; pair = true; break;
+    }
+    return "fht_pass_kernel<" + std::to_string(threads) + ", " + src + ", " + lds + ", " + dst +
+           ", " + (first ? "true" : "false") + ", " + (table ? "true" : "false") + ", " +
+           (pair ? "true" : "false") + ">";
+}
 
 struct DevTables {
     int device = -1;
@@ -162,28 +203,55 @@ struct fht_plan_s {
         return FHT_OK;
     }
 
-    // The job of quadrant q in its pass `level`; workspace offsets are absolute
+    bool narrow(int v, size_t p) const { return axis[v].passes[p].max_root_w <= kNarrowWidth; }
+
+    // Pass p of lane view v runs both quadrants of the view as pairs: uint8
+    // images with both quadrants selected, while the pass keeps 16-bit sums
+    // and in the pass that outgrows them.
+    bool pair_pass(int v, size_t p) const
+    {
+        return dtype == FHT_U8 && ((qmask >> (2 * v)) & 3u) == 3u &&
+               (p == 0 || narrow(v, p) || narrow(v, p - 1));
+    }
+
+    // Pass p leaves pair rows (16-bit sums packed in 32 bits) in the workspace.
+    bool pair_rows(int v, size_t p) const { return pair_pass(v, p) && (p == 0 || narrow(v, p)); }
+
+    // The job of slot r in its pass `level`; workspace offsets are absolute
     // (ws != null) or relative to the workspace (ws == null, batch tables).
-    JobDesc job(int q, int level, const void *img, void *out, char *ws, size_t ws_base) const
+    // Pair rows live in the buffers of the pair's positive-slope quadrant.
+    JobDesc job(JobRef r, int level, const void *img, void *out, char *ws, size_t ws_base) const
     {
         JobDesc jd;
         std::memset(&jd, 0, sizeof(jd));
-        const fht::AxisPlan &ax = axis[q >> 1];
+        const int q = r.q, v = q >> 1;
+        const fht::AxisPlan &ax = axis[v];
         const bool final = level == npass[q] - 1;
-        int flags = ((q >> 1) ? fht::JF_COLS : 0) | ((q & 1) ? fht::JF_MIRROR : 0) |
-                    (final ? fht::JF_FINAL : 0);
+        int flags = (v ? fht::JF_COLS : 0) | (final ? fht::JF_FINAL : 0);
+        if (r.pair)
+            flags |= fht::JF_PAIR;
+        else if (q & 1)
+            flags |= fht::JF_MIRROR;
+        auto ws_ptr = [&](int qq, int buf) {
+            const size_t off = ws_base + ws_off[qq][buf];
+            return ws ? static_cast<void *>(ws + off) : reinterpret_cast<void *>(off);
+        };
         if (level == 0) {
             jd.src = img;
         } else {
-            const size_t off = ws_base + ws_off[q][(level - 1) & 1];
-            jd.src = ws ? static_cast<const void *>(ws + off) : reinterpret_cast<const void *>(off);
+            jd.src = ws_ptr(pair_rows(v, level - 1) ? (q & ~1) : q, (level - 1) & 1);
             if (!ws) flags |= fht::JF_SRC_WS;
         }
         if (final) {
             jd.dst = static_cast<char *>(out) + out_off[q] * acc_bytes(dtype);
+            if (r.pair) jd.dst2 = static_cast<char *>(out) + out_off[q + 1] * acc_bytes(dtype);
+        } else if (r.pair && !pair_rows(v, level)) {
+            // the pass that outgrows 16 bits splits the pairs into two row sets
+            jd.dst = ws_ptr(q, level & 1);
+            jd.dst2 = ws_ptr(q + 1, level & 1);
+            if (!ws) flags |= fht::JF_DST_WS;
         } else {
-            const size_t off = ws_base + ws_off[q][level & 1];
-            jd.dst = ws ? static_cast<void *>(ws + off) : reinterpret_cast<void *>(off);
+            jd.dst = ws_ptr(q, level & 1);
             if (!ws) flags |= fht::JF_DST_WS;
         }
         jd.H = ax.H;
@@ -240,7 +308,7 @@ fht_status make_schedule(const fht_schedule *sched, fht::Schedule *sc)
         sc->s_tile_first % fht::kChunk || !valid_threads(sc->threads) ||
         !valid_threads(sc->threads_first) || sc->first_levels < 1 ||
         sc->first_levels > fht::kMaxFirstLevels || sc->max_levels < 1 ||
-        sc->max_levels > fht::kMaxSteps || sc->lds_budget < 1024 || sc->lds_budget > 65536 ||
+        sc->max_levels > fht::kMaxSteps || sc->lds_budget < 1024 || sc->lds_budget > 163840 ||
         sc->t_tile < 0 || sc->t_tile > 4096)
         return FHT_EINVAL;
     return FHT_OK;
@@ -255,8 +323,8 @@ fht_status forward_one(fht_plan plan, const DevTables *t, size_t l, const void *
     a.items = reinterpret_cast<const int4 *>(t->items[l]);
     a.hdrs = t->hdrs;
     a.ops = reinterpret_cast<const int4 *>(t->ops);
-    for (size_t j = 0; j < L.jobs_q.size(); ++j)
-        a.inl[j] = plan->job(L.jobs_q[j], L.level, d_img, d_out, static_cast<char *>(d_ws), 0);
+    for (size_t j = 0; j < L.jobs.size(); ++j)
+        a.inl[j] = plan->job(L.jobs[j], L.level, d_img, d_out, static_cast<char *>(d_ws), 0);
     const int nitems = static_cast<int>(L.items.size() / 4);
     return hip_status(fht::launch_pass(L.combo, a, nitems, L.lds_bytes, L.threads,
                                        static_cast<hipStream_t>(stream)));
@@ -346,9 +414,9 @@ fht_status batch_prepare(fht_batch_s *b, const fht_plan *plans, int32_t n,
             }
             Launch &B = b->launches[found->second];
             std::vector<int> slot;
-            for (int q : L.jobs_q) {
+            for (const JobRef &r : L.jobs) {
                 slot.push_back(static_cast<int>(jobs.size()));
-                jobs.push_back(p->job(q, L.level, d_imgs[i], d_outs[i], nullptr, ws_base));
+                jobs.push_back(p->job(r, L.level, d_imgs[i], d_outs[i], nullptr, ws_base));
             }
             for (size_t k4 = 0; k4 < L.items.size(); k4 += 4) {
                 B.items.push_back(L.items[k4] + hdr_base[u]);
@@ -450,8 +518,14 @@ fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, fht_dtype 
         for (int v = 0; v < 2; ++v) {
             if (!(quadrant_mask & (3u << (2 * v)))) continue;
             const int W = v == 0 ? rows : cols, H = v == 0 ? cols : rows;
+            // both quadrants of a uint8 view run as 16-bit pairs: 4-byte LDS elements
+            fht::ElemRule vrule = rule;
+            if (dtype == FHT_U8 && ((quadrant_mask >> (2 * v)) & 3u) == 3u) {
+                vrule.narrow_bytes = 4;
+                vrule.transition_bytes = 8;
+            }
             std::string err;
-            if (!fht::plan_axis(W, H, static_cast<int>(split), rule, sc, &p->axis[v], &err)) {
+            if (!fht::plan_axis(W, H, static_cast<int>(split), vrule, sc, &p->axis[v], &err)) {
                 delete p;
                 return FHT_EINVAL;
             }
@@ -513,8 +587,10 @@ fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, fht_dtype 
             for (int q = 0; q < 4; ++q) {
                 if (!(quadrant_mask & (1u << q)) || p->npass[q] <= l) continue;
                 const int v = q >> 1;
+                const bool pair = p->pair_pass(v, l);
+                if (pair && (q & 1)) continue;  // run by the pair job of q - 1
                 const fht::Pass &ps = p->axis[v].passes[l];
-                const Combo combo = pass_combo(dtype, p->axis[v], l);
+                const Combo combo = pass_combo(dtype, p->axis[v], l, pair);
                 Launch *L = nullptr;
                 for (size_t k : level_launches)
                     if (p->launches[k].combo == combo) L = &p->launches[k];
@@ -525,9 +601,10 @@ fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, fht_dtype 
                     L->level = l;
                     L->combo = combo;
                     L->threads = l == 0 ? sc.threads_first : sc.threads;
+                    L->kernel = kernel_name(combo, L->threads, false);
                 }
-                const int job = static_cast<int>(L->jobs_q.size());
-                L->jobs_q.push_back(q);
+                const int job = static_cast<int>(L->jobs.size());
+                L->jobs.push_back(JobRef{q, pair});
                 for (size_t i = 0; i < ps.items.size(); i += 4) {
                     L->items.push_back(ps.items[i] + p->prog_base[v][l]);
                     L->items.push_back(job);
@@ -578,26 +655,39 @@ fht_status fht_plan_launch_info(fht_plan plan, int32_t launch, int32_t *level,
     case Combo::I32_I32_I32: in_b = 4; out_b = 4; break;
     case Combo::F32_FIRST: case Combo::F32_LATER: in_b = 4; out_b = 4; break;
     case Combo::F64_FIRST: case Combo::F64_LATER: in_b = 8; out_b = 8; break;
+    case Combo::P_U8_FIRST: in_b = 1; out_b = 2; break;
+    case Combo::P_U8_FIRST_FINAL: in_b = 1; out_b = 4; break;
+    case Combo::P_U16_MID: in_b = 2; out_b = 2; break;
+    case Combo::P_U16_MID_FINAL: in_b = 2; out_b = 4; break;
+    case Combo::P_I32: in_b = 2; out_b = 4; break;
     }
     int64_t bin = 0, bout = 0;
     bool image_counted = false;
-    for (int q : L.jobs_q) {
-        const fht::AxisPlan &ax = plan->axis[q >> 1];
+    for (const JobRef &r : L.jobs) {
+        const fht::AxisPlan &ax = plan->axis[r.q >> 1];
         const int64_t wh = static_cast<int64_t>(ax.W) * ax.H;
-        if (L.level == 0) {
-            // every quadrant of a launch reads the same image; count it once
-            if (!image_counted) bin += static_cast<int64_t>(plan->R) * plan->C * in_b;
-            image_counted = true;
-        } else {
-            bin += wh * in_b;
+        for (int c = 0; c < (r.pair ? 2 : 1); ++c) {
+            if (L.level == 0) {
+                // every quadrant of a launch reads the same image; count it once
+                if (!image_counted) bin += static_cast<int64_t>(plan->R) * plan->C * in_b;
+                image_counted = true;
+            } else {
+                bin += wh * in_b;
+            }
+            bout += wh * out_b;
         }
-        bout += wh * out_b;
     }
     if (level) *level = L.level;
     if (bytes_in) *bytes_in = bin;
     if (bytes_out) *bytes_out = bout;
     if (n_items) *n_items = static_cast<int32_t>(L.items.size() / 4);
     return FHT_OK;
+}
+
+const char *fht_plan_launch_kernel(fht_plan plan, int32_t launch)
+{
+    if (!plan || launch < 0 || launch >= static_cast<int32_t>(plan->launches.size())) return nullptr;
+    return plan->launches[launch].kernel.c_str();
 }
 
 fht_status fht_plan_upload(fht_plan plan)

@@ -19,6 +19,8 @@
 // all of a wavefront's rows in flight at once.
 #include "kernels.hpp"
 
+#include <type_traits>
+
 namespace fht {
 
 namespace {
@@ -50,6 +52,7 @@ __device__ __forceinline__ JobDesc pick_job(const PassArgs &a, int j)
         JobDesc d;
         d.src = p->src;
         d.dst = p->dst;
+        d.dst2 = p->dst2;
         d.H = p->H;
         d.ld = p->ld;
         d.flags = p->flags;
@@ -64,12 +67,15 @@ __device__ __forceinline__ JobDesc pick_job(const PassArgs &a, int j)
     }
 }
 
-// (base + c) mod H for 0 <= base < H, c >= 0.
+// p mod H for p >= 0; ONE promises p < 2 H (one conditional subtraction, no
+// division), which the callers check once per row or item.
+template <bool ONE>
 __device__ __forceinline__ int wrap(int p, int H)
 {
-    if (p >= H) p -= H;
-    if (p >= H) p %= H;
-    return p;
+    if constexpr (ONE)
+        return p >= H ? p - H : p;
+    else
+        return p % H;
 }
 
 // Descriptors of this wavefront's entries g + NW * lane of a table of n entries.
@@ -123,14 +129,26 @@ __device__ __forceinline__ void merge_group(TL *lds, const int4 &mine, int m, in
     }
 }
 
+// A source element as an LDS element: pair rows (two 16-bit sums in 32 bits)
+// become two 32-bit sums when the LDS holds 32-bit pairs.
+template <typename TL, typename TS>
+__device__ __forceinline__ TL widen(TS v)
+{
+    if constexpr (std::is_same<TL, uint2>::value)
+        return make_uint2(static_cast<uint32_t>(v) & 0xffffu, static_cast<uint32_t>(v) >> 16);
+    else
+        return static_cast<TL>(v);
+}
+
 // Later-pass loads {dst, row, offset, K}: lds[dst + c] = src[row][(s0 + offset + c) mod H].
 // Rows go straight from HBM into 32-bit LDS elements when the LDS type is
 // 32-bit (global_load_lds_dword; the 16-bit form zero-extends each lane's
 // value into its dword, which widens 16-bit rows on the way); other rows go
 // through registers, four rows of loads in flight before their LDS writes.
-template <int K, int NW, typename TS, typename TL>
-__device__ __forceinline__ void load_rows(TL *lds, const int4 *ent, int n, const TS *src, int H,
-                                          int s0, int wave, int lane)
+// ONE: every row window wraps around at most once (H >= 64 K).
+template <int K, int NW, typename TS, typename TL, bool ONE>
+__device__ __forceinline__ void load_rows_impl(TL *lds, const int4 *ent, int n, const TS *src,
+                                               int H, int s0, int wave, int lane)
 {
     for (int g = wave; g < n; g += 64 * NW) {
         const int4 mine = fetch_desc<NW>(ent, n, g, lane);
@@ -143,7 +161,7 @@ __device__ __forceinline__ void load_rows(TL *lds, const int4 *ent, int n, const
                 TL *dst = lds + rl(mine.x, j);
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const TS *gp = rowp + wrap(base + 64 * k + lane, H);
+                    const TS *gp = rowp + static_cast<uint32_t>(wrap<ONE>(base + 64 * k + lane, H));
                     auto *g1 = (const __attribute__((address_space(1))) void *)(gp);
                     auto *l3 = (__attribute__((address_space(3))) void *)(dst + 64 * k);
                     if constexpr (sizeof(TS) == 2)
@@ -164,7 +182,7 @@ __device__ __forceinline__ void load_rows(TL *lds, const int4 *ent, int n, const
                     const TS *rowp = src + static_cast<size_t>(rl(mine.y, j)) * H;
 #pragma unroll
                     for (int k = 0; k < K; ++k)
-                        v[r][k] = static_cast<TL>(rowp[wrap(base + 64 * k + lane, H)]);
+                        v[r][k] = widen<TL>(rowp[static_cast<uint32_t>(wrap<ONE>(base + 64 * k + lane, H))]);
                 }
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
@@ -179,6 +197,16 @@ __device__ __forceinline__ void load_rows(TL *lds, const int4 *ent, int n, const
     }
 }
 
+template <int K, int NW, typename TS, typename TL>
+__device__ __forceinline__ void load_rows(TL *lds, const int4 *ent, int n, const TS *src, int H,
+                                          int s0, int wave, int lane)
+{
+    if (H >= 64 * K)
+        load_rows_impl<K, NW, TS, TL, true>(lds, ent, n, src, H, s0, wave, lane);
+    else
+        load_rows_impl<K, NW, TS, TL, false>(lds, ent, n, src, H, s0, wave, lane);
+}
+
 // First-pass loads: the lanes of the pass root (at most 64, one descriptor
 // {dst, lane, window start, K} each, in lane order) times their K-chunk
 // position windows, read from the image.  Lanes are image rows (positions
@@ -186,68 +214,116 @@ __device__ __forceinline__ void load_rows(TL *lds, const int4 *ent, int n, const
 // thread mapping follows the contiguous direction so that loads coalesce.
 //   rows: wavefront w takes lanes w + NW i, two lanes at a time
 //   cols: thread t takes lane t % XW and positions t / XW + k * (threads / XW)
-template <int K, int NW, typename TSrc, typename TL>
-__device__ __forceinline__ void load_image(TL *lds, const int4 *ent, int nl, int load_end,
-                                           const TSrc *img, const JobDesc &job, int s0, int wave,
-                                           int lane)
+// Every thread issues all its loads (clamped in bounds) before the first LDS
+// write, so they are in flight together.  With PAIR every element is
+// (value at y) | (value at the mirrored position (H - y) mod H) << 16: the
+// positive- and negative-slope quadrants together.  ONE: the windows wrap
+// around at most once (load_end <= H).
+template <typename TL, typename TSrc, bool PAIR>
+__device__ __forceinline__ TL image_elem(TSrc a, TSrc b)
+{
+    if constexpr (PAIR)
+        return static_cast<TL>(a) | (static_cast<TL>(b) << 16);
+    else
+        return static_cast<TL>(a);
+}
+
+template <int K, int NW, typename TSrc, typename TL, bool PAIR, bool ONE>
+__device__ __forceinline__ void load_image_impl(TL *lds, const int4 *ent, int nl, int load_end,
+                                                const TSrc *img, const JobDesc &job, int s0,
+                                                int wave, int lane)
 {
     const int H = job.H;
-    const bool mirror = job.flags & JF_MIRROR;
+    const size_t ld = static_cast<size_t>(job.ld);
+    const bool mirror = !PAIR && (job.flags & JF_MIRROR);
     if (job.flags & JF_COLS) {
         const int XW = nl <= 32 ? 32 : 64;
         const int x = threadIdx.x % XW, pstep = 64 * NW / XW;
-        int4 mine = make_int4(0, 0, 0, 0);
-        if (x < nl) mine = ent[x];
+        const bool xin = x < nl;
+        const int4 mine = ent[xin ? x : nl - 1];
         const int wend = mine.z + 64 * K;
+        const TSrc *colp = img + mine.y;
         constexpr int U = 8;
         for (int p0 = threadIdx.x / XW; p0 < load_end; p0 += pstep * U) {
-            TL v[U];
+            TSrc a[U], b[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int p = min(p0 + u * pstep, load_end - 1);
-                int y = wrap(s0 + p, H);
-                if (mirror && y != 0) y = H - y;
-                v[u] = (x < nl) ? static_cast<TL>(img[static_cast<size_t>(y) * job.ld + mine.y]) : TL(0);
+                const int y = wrap<ONE>(s0 + p, H);
+                const int ym = y != 0 ? H - y : 0;
+                a[u] = colp[(mirror ? ym : y) * ld];
+                if constexpr (PAIR) b[u] = colp[ym * ld];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int p = p0 + u * pstep;
-                if (x < nl && p < load_end && p >= mine.z && p < wend) lds[mine.x + p - mine.z] = v[u];
+                if (xin && p < load_end && p >= mine.z && p < wend)
+                    lds[mine.x + p - mine.z] = image_elem<TL, TSrc, PAIR>(a[u], b[u]);
             }
         }
     } else {
-        int4 mine = make_int4(0, 0, 0, 0);
-        if (lane < nl) mine = ent[lane];
+        const int4 mine = ent[lane < nl ? lane : nl - 1];
         for (int x0 = wave; x0 < nl; x0 += 2 * NW) {
             const int x1 = min(x0 + NW, nl - 1);
             const bool two = x0 + NW < nl;
-            TL v[2 * K];
+            TSrc a[2 * K], b[2 * K];
 #pragma unroll
             for (int q = 0; q < 2 * K; ++q) {
                 const int x = q < K ? x0 : x1;
                 const int k = q < K ? q : q - K;
-                int base = s0 + rl(mine.z, x);
-                if (base >= H) base %= H;
-                int y = wrap(base + 64 * k + lane, H);
-                if (mirror && y != 0) y = H - y;
-                v[q] = static_cast<TL>(img[static_cast<size_t>(rl(mine.y, x)) * job.ld + y]);
+                const int y = wrap<ONE>(s0 + rl(mine.z, x) + 64 * k + lane, H);
+                const int ym = y != 0 ? H - y : 0;
+                const TSrc *rowp = img + static_cast<size_t>(rl(mine.y, x)) * ld;
+                a[q] = rowp[mirror ? ym : y];
+                if constexpr (PAIR) b[q] = rowp[ym];
             }
 #pragma unroll
             for (int q = 0; q < 2 * K; ++q) {
                 const int x = q < K ? x0 : x1;
                 const int k = q < K ? q : q - K;
-                if (q < K || two) lds[rl(mine.x, x) + 64 * k + lane] = v[q];
+                if (q < K || two) lds[rl(mine.x, x) + 64 * k + lane] = image_elem<TL, TSrc, PAIR>(a[q], b[q]);
             }
         }
     }
 }
 
+template <int K, int NW, typename TSrc, typename TL, bool PAIR>
+__device__ __forceinline__ void load_image(TL *lds, const int4 *ent, int nl, int load_end,
+                                           const TSrc *img, const JobDesc &job, int s0, int wave,
+                                           int lane)
+{
+    if (load_end <= job.H)
+        load_image_impl<K, NW, TSrc, TL, PAIR, true>(lds, ent, nl, load_end, img, job, s0, wave, lane);
+    else
+        load_image_impl<K, NW, TSrc, TL, PAIR, false>(lds, ent, nl, load_end, img, job, s0, wave, lane);
+}
+
 // Stores {src, row, limit, K}: dst[row][s0 + c] = lds[src + c] for c < limit
 // and s0 + c < H; the final output of a negative-slope quadrant is written
 // back in un-mirrored position order.
-template <int K, int NW, typename TL, typename TD>
-__device__ __forceinline__ void store_rows(const TL *lds, const int4 *ent, int n, TD *dst, int H,
-                                           int s0, bool unmirror, int wave, int lane)
+// The two sums of a pair element: 16-bit halves of 32 bits, or the
+// components of a 32-bit pair.
+template <typename TL>
+__device__ __forceinline__ uint32_t pair_lo(TL v)
+{
+    if constexpr (std::is_same<TL, uint2>::value) return v.x;
+    else return static_cast<uint32_t>(v) & 0xffffu;
+}
+
+template <typename TL>
+__device__ __forceinline__ uint32_t pair_hi(TL v)
+{
+    if constexpr (std::is_same<TL, uint2>::value) return v.y;
+    else return static_cast<uint32_t>(v) >> 16;
+}
+
+// With PAIR_OUT each pair is split into two int32 rows: the positive-slope
+// sum to dst, the negative-slope sum (mirrored frame) to dst2, stored at the
+// un-mirrored position when `unmirror` (the final output).
+template <int K, int NW, typename TL, typename TD, bool PAIR_OUT>
+__device__ __forceinline__ void store_rows(const TL *lds, const int4 *ent, int n, TD *dst,
+                                           TD *dst2, int H, int s0, bool unmirror, int wave,
+                                           int lane)
 {
     for (int g = wave; g < n; g += 64 * NW) {
         const int4 mine = fetch_desc<NW>(ent, n, g, lane);
@@ -255,7 +331,8 @@ __device__ __forceinline__ void store_rows(const TL *lds, const int4 *ent, int n
         for (int j = 0; j < m; ++j) {
             const int lim = min(rl(mine.z, j), H - s0);
             const TL *srcp = lds + rl(mine.x, j) + lane;
-            TD *rowp = dst + static_cast<size_t>(rl(mine.y, j)) * H;
+            const size_t row = static_cast<size_t>(rl(mine.y, j)) * H;
+            TD *rowp = dst + row;
             TL v[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) v[k] = srcp[64 * k];
@@ -264,16 +341,23 @@ __device__ __forceinline__ void store_rows(const TL *lds, const int4 *ent, int n
                 const int c = 64 * k + lane;
                 if (c < lim) {
                     const int s = s0 + c;
-                    rowp[(unmirror && s != 0) ? H - s : s] = static_cast<TD>(v[k]);
+                    const int sm = s != 0 ? H - s : 0;
+                    if constexpr (PAIR_OUT) {
+                        rowp[s] = static_cast<TD>(pair_lo(v[k]));
+                        dst2[row + (unmirror ? sm : s)] = static_cast<TD>(pair_hi(v[k]));
+                    } else {
+                        rowp[unmirror ? sm : s] = static_cast<TD>(v[k]);
+                    }
                 }
             }
         }
     }
 }
 
-template <int NT, int K, typename TSrc, typename TL, typename TD, bool FROM_IMAGE>
+template <int NT, int K, typename TSrc, typename TL, typename TD, bool FROM_IMAGE, bool PAIR>
 __device__ __forceinline__ void run_item(TL *lds, cptr<int32_t> hdr, const int4 *ent,
-                                         const JobDesc &job, const char *src, char *dst, int s0)
+                                         const JobDesc &job, const char *src, char *dst,
+                                         char *dst2, int s0)
 {
     constexpr int NW = NT / 64;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -287,8 +371,8 @@ __device__ __forceinline__ void run_item(TL *lds, cptr<int32_t> hdr, const int4 
     int4 cur = fetch_desc<NW>(step_ent, cnt, wave, lane);
 
     if constexpr (FROM_IMAGE) {
-        load_image<K, NW, TSrc, TL>(lds, ent, nload, hdr[24], reinterpret_cast<const TSrc *>(src),
-                                    job, s0, wave, lane);
+        load_image<K, NW, TSrc, TL, PAIR>(lds, ent, nload, hdr[24],
+                                          reinterpret_cast<const TSrc *>(src), job, s0, wave, lane);
     } else {
         load_rows<K, NW, TSrc, TL>(lds, ent, nload, reinterpret_cast<const TSrc *>(src), H, s0,
                                    wave, lane);
@@ -310,9 +394,10 @@ __device__ __forceinline__ void run_item(TL *lds, cptr<int32_t> hdr, const int4 
     }
     __syncthreads();
 
-    const bool unmirror = (job.flags & JF_FINAL) && (job.flags & JF_MIRROR);
-    store_rows<K, NW, TL, TD>(lds, step_ent, nstore, reinterpret_cast<TD *>(dst), H, s0,
-                              unmirror, wave, lane);
+    constexpr bool PAIR_OUT = PAIR && sizeof(TD) == 4 && std::is_signed<TD>::value;
+    const bool unmirror = (job.flags & JF_FINAL) && (PAIR_OUT || (job.flags & JF_MIRROR));
+    store_rows<K, NW, TL, TD, PAIR_OUT>(lds, step_ent, nstore, reinterpret_cast<TD *>(dst),
+                                        reinterpret_cast<TD *>(dst2), H, s0, unmirror, wave, lane);
 }
 
 // TSrc / TL / TD: element types read, kept in LDS and written (see Combo).
@@ -322,7 +407,7 @@ __device__ __forceinline__ void run_item(TL *lds, cptr<int32_t> hdr, const int4 
 // dealt to the eight XCDs round robin, so this gives each XCD a contiguous
 // range of items and neighbouring tiles, which read overlapping rows, share
 // an L2.
-template <int NT, typename TSrc, typename TL, typename TD, bool FROM_IMAGE, bool TABLE>
+template <int NT, typename TSrc, typename TL, typename TD, bool FROM_IMAGE, bool TABLE, bool PAIR>
 __global__ void __launch_bounds__(NT) fht_pass_kernel(PassArgs args, int n_items)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -339,34 +424,38 @@ __global__ void __launch_bounds__(NT) fht_pass_kernel(PassArgs args, int n_items
     const char *src = static_cast<const char *>(job.src);
     if (job.flags & JF_SRC_WS) src = args.ws + reinterpret_cast<uintptr_t>(job.src);
     char *dst = static_cast<char *>(job.dst);
-    if (job.flags & JF_DST_WS) dst = args.ws + reinterpret_cast<uintptr_t>(job.dst);
+    char *dst2 = static_cast<char *>(job.dst2);
+    if (job.flags & JF_DST_WS) {
+        dst = args.ws + reinterpret_cast<uintptr_t>(job.dst);
+        dst2 = args.ws + reinterpret_cast<uintptr_t>(job.dst2);
+    }
 
     switch (hdr[26]) {
-    case 1: run_item<NT, 1, TSrc, TL, TD, FROM_IMAGE>(lds, hdr, ent, job, src, dst, item.z); break;
-    case 2: run_item<NT, 2, TSrc, TL, TD, FROM_IMAGE>(lds, hdr, ent, job, src, dst, item.z); break;
-    case 3: run_item<NT, 3, TSrc, TL, TD, FROM_IMAGE>(lds, hdr, ent, job, src, dst, item.z); break;
-    default: run_item<NT, 4, TSrc, TL, TD, FROM_IMAGE>(lds, hdr, ent, job, src, dst, item.z); break;
+    case 1: run_item<NT, 1, TSrc, TL, TD, FROM_IMAGE, PAIR>(lds, hdr, ent, job, src, dst, dst2, item.z); break;
+    case 2: run_item<NT, 2, TSrc, TL, TD, FROM_IMAGE, PAIR>(lds, hdr, ent, job, src, dst, dst2, item.z); break;
+    case 3: run_item<NT, 3, TSrc, TL, TD, FROM_IMAGE, PAIR>(lds, hdr, ent, job, src, dst, dst2, item.z); break;
+    default: run_item<NT, 4, TSrc, TL, TD, FROM_IMAGE, PAIR>(lds, hdr, ent, job, src, dst, dst2, item.z); break;
     }
 }
 
-template <int NT, typename TSrc, typename TL, typename TD, bool FROM_IMAGE>
+template <int NT, typename TSrc, typename TL, typename TD, bool FROM_IMAGE, bool PAIR>
 hipError_t launch_nt(const PassArgs &args, int n_items, int lds_bytes, hipStream_t stream)
 {
     const dim3 grid((n_items + 7) / 8 * 8), block(NT);
     if (args.jobs)
-        fht_pass_kernel<NT, TSrc, TL, TD, FROM_IMAGE, true><<<grid, block, lds_bytes, stream>>>(args, n_items);
+        fht_pass_kernel<NT, TSrc, TL, TD, FROM_IMAGE, true, PAIR><<<grid, block, lds_bytes, stream>>>(args, n_items);
     else
-        fht_pass_kernel<NT, TSrc, TL, TD, FROM_IMAGE, false><<<grid, block, lds_bytes, stream>>>(args, n_items);
+        fht_pass_kernel<NT, TSrc, TL, TD, FROM_IMAGE, false, PAIR><<<grid, block, lds_bytes, stream>>>(args, n_items);
     return hipGetLastError();
 }
 
-template <typename TSrc, typename TL, typename TD, bool FROM_IMAGE>
+template <typename TSrc, typename TL, typename TD, bool FROM_IMAGE, bool PAIR = false>
 hipError_t launch_typed(const PassArgs &args, int n_items, int lds_bytes, int threads,
                         hipStream_t stream)
 {
     if (threads == 512)
-        return launch_nt<512, TSrc, TL, TD, FROM_IMAGE>(args, n_items, lds_bytes, stream);
-    return launch_nt<256, TSrc, TL, TD, FROM_IMAGE>(args, n_items, lds_bytes, stream);
+        return launch_nt<512, TSrc, TL, TD, FROM_IMAGE, PAIR>(args, n_items, lds_bytes, stream);
+    return launch_nt<256, TSrc, TL, TD, FROM_IMAGE, PAIR>(args, n_items, lds_bytes, stream);
 }
 
 }  // namespace
@@ -386,6 +475,11 @@ hipError_t launch_pass(Combo combo, const PassArgs &args, int n, int lds, int th
     case Combo::F32_LATER: return launch_typed<float, float, float, false>(args, n, lds, threads, stream);
     case Combo::F64_FIRST: return launch_typed<double, double, double, true>(args, n, lds, threads, stream);
     case Combo::F64_LATER: return launch_typed<double, double, double, false>(args, n, lds, threads, stream);
+    case Combo::P_U8_FIRST: return launch_typed<uint8_t, uint32_t, uint32_t, true, true>(args, n, lds, threads, stream);
+    case Combo::P_U8_FIRST_FINAL: return launch_typed<uint8_t, uint32_t, int32_t, true, true>(args, n, lds, threads, stream);
+    case Combo::P_U16_MID: return launch_typed<uint32_t, uint32_t, uint32_t, false, true>(args, n, lds, threads, stream);
+    case Combo::P_U16_MID_FINAL: return launch_typed<uint32_t, uint32_t, int32_t, false, true>(args, n, lds, threads, stream);
+    case Combo::P_I32: return launch_typed<uint32_t, uint2, int32_t, false, true>(args, n, lds, threads, stream);
     }
     return hipErrorInvalidValue;
 }

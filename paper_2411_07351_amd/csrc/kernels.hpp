@@ -7,10 +7,11 @@
 
 namespace fht {
 
-// One (image, quadrant, pass) job of a launch.
+// One (image, quadrant or quadrant pair, pass) job of a launch.
 struct JobDesc {
     const void *src;  // image (first pass) or the previous pass's [W][H] rows
     void *dst;        // next pass's [W][H] rows or the final output
+    void *dst2;       // pair jobs, final pass: output of the negative-slope quadrant
     int32_t H;        // positions per lane
     int32_t ld;       // image row stride in elements (first pass only)
     int32_t flags;    // JF_* bits
@@ -23,6 +24,8 @@ enum : int32_t {
     JF_FINAL = 4,       // dst is the final output (stored un-mirrored)
     JF_SRC_WS = 8,      // src is an offset into the launch workspace
     JF_DST_WS = 16,     // dst is an offset into the launch workspace
+    JF_PAIR = 32,       // the job runs both quadrants of a lane view as pairs
+                        // (positive slope low, mirrored negative slope high)
 };
 
 constexpr int kInlineJobs = 4;
@@ -51,6 +54,16 @@ enum class Combo {
     F32_LATER,
     F64_FIRST,     // first pass, float64 image
     F64_LATER,
+    // Quadrant pairs (JF_PAIR): the positive- and negative-slope quadrants of
+    // one lane view share the order tree and every program, so one work item
+    // runs both, adding 16-bit pairs with one 32-bit add (no carry crosses
+    // the halves: each stays below 2^16 while nodes are at most 257 wide).
+    P_U8_FIRST,        // first pass, uint8 image, pair rows out
+    P_U8_FIRST_FINAL,  // first pass, two final int32 outputs
+    P_U16_MID,         // later pass, pair rows in and out
+    P_U16_MID_FINAL,   // later pass, pair rows in, two final int32 outputs
+    P_I32,             // the pass that outgrows 16 bits: pair rows in, 32-bit pairs in
+                       // LDS, two int32 row sets (or final outputs) out
 };
 
 // Enqueues one fused pass of `n_items` work items with `threads` (256 or

@@ -337,7 +337,7 @@ bool plan_axis(int W, int H, int split, const ElemRule &rule, const Schedule &sc
         const int hi = std::min(L, lin + maxlv);
         const int lo = (L > lin) ? lin + 1 : lin;
         for (int lout = hi; lout >= lo && !found; --lout) {
-            const int eb = rule.bytes_for(frontier_width(tr, lout));
+            const int eb = rule.bytes_for(frontier_width(tr, lin), frontier_width(tr, lout));
             const int budget_elems = sched.lds_budget / eb;
             const int pad = eb == 2 ? 2 : 1;  // skew rows by one 32-bit bank
             // The first pass takes whole roots (at most 64 lanes, loaded as one

@@ -44,13 +44,13 @@ Tree make_tree(int W, int split);
 // position tile whose widest window fits its target width.
 struct Schedule {
     int s_tile = 192;         // target window width, later passes
-    int s_tile_first = 192;   // target window width, first pass
+    int s_tile_first = 128;   // target window width, first pass
     int first_levels = 5;
     int max_levels = 3;
     int lds_budget = 64 * 1024;
     int t_tile = 16;          // 0: the largest of 32, 16, 8, 4 that fits
-    int threads = 256;        // threads per workgroup of later passes: 256 or 512
-    int threads_first = 256;  // threads per workgroup of the first pass
+    int threads = 512;        // threads per workgroup of later passes: 256 or 512
+    int threads_first = 512;  // threads per workgroup of the first pass
 };
 
 // One fused pass: from the frontier of level lin (maximal nodes of height
@@ -74,12 +74,19 @@ struct AxisPlan {
     std::vector<Pass> passes;
 };
 
-// LDS element size of a pass as a function of the widest node it produces:
-// `narrow_bytes` while that width is at most `narrow_width`, else `wide_bytes`
-// (uint8 images: 16-bit sums up to 257 lanes, then 32-bit).
+// LDS element size of a pass as a function of the widest nodes it reads and
+// produces: `narrow_bytes` while the output width is at most `narrow_width`,
+// `transition_bytes` (if set) for the pass that crosses it, else `wide_bytes`
+// (uint8 images: 16-bit sums up to 257 lanes, then 32-bit; quadrant pairs keep
+// two sums per element).
 struct ElemRule {
-    int narrow_bytes = 4, wide_bytes = 4, narrow_width = 0;
-    int bytes_for(int width) const { return width <= narrow_width ? narrow_bytes : wide_bytes; }
+    int narrow_bytes = 4, wide_bytes = 4, narrow_width = 0, transition_bytes = 0;
+    int bytes_for(int in_width, int out_width) const
+    {
+        if (out_width <= narrow_width) return narrow_bytes;
+        if (transition_bytes && in_width <= narrow_width) return transition_bytes;
+        return wide_bytes;
+    }
 };
 
 // Plans the passes for W lanes of H positions.  Returns false and sets *err

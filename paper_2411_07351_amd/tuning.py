@@ -17,20 +17,20 @@ from typing import Sequence
 
 from . import _binding as B
 
-DEFAULT = dict(s_tile=192, s_tile_first=192, first_levels=5, max_levels=3, t_tile=16,
-               threads=256, threads_first=256, lds_budget=65536)
+DEFAULT = dict(s_tile=192, s_tile_first=128, first_levels=5, max_levels=3, t_tile=16,
+               threads=512, threads_first=512, lds_budget=65536)
 
 # A modest candidate set around the default: fused depth of the first pass,
 # window targets, slope tile and workgroup size of the later passes.
 CANDIDATES = [
     DEFAULT,
-    dict(DEFAULT, t_tile=8),
-    dict(DEFAULT, s_tile=256),
-    dict(DEFAULT, s_tile=128),
-    dict(DEFAULT, threads=512, t_tile=32, max_levels=6),
-    dict(DEFAULT, first_levels=4, max_levels=4),
-    dict(DEFAULT, s_tile_first=256, threads_first=512),
-    dict(DEFAULT, max_levels=4, t_tile=16),
+    dict(DEFAULT, t_tile=8, threads=256),
+    dict(DEFAULT, s_tile=128, threads=256),
+    dict(DEFAULT, s_tile=256, lds_budget=131072),
+    dict(DEFAULT, s_tile_first=192),
+    dict(DEFAULT, first_levels=4, s_tile_first=192),
+    dict(DEFAULT, threads_first=256),
+    dict(DEFAULT, max_levels=4),
     dict(DEFAULT, max_levels=2),
 ]
 
