@@ -14,6 +14,9 @@
 #include <atomic>
 #include <cstring>
 #include <deque>
+#include <list>
+#include <memory>
+#include <tuple>
 #include <map>
 #include <mutex>
 #include <new>
@@ -120,23 +123,188 @@ std::string kernel_name(Combo c, int threads, bool table)
            (pair ? "true" : "false") + ">";
 }
 
-struct DevTables {
+// Device copy of one lane view's tile programs.
+struct DevProgs {
     int device = -1;
     int32_t *hdrs = nullptr;
-    int32_t *ops = nullptr;
-    std::vector<int32_t *> items;  // per launch
+    int4 *ops = nullptr;
+};
+
+// One lane view's tile programs, shared by every plan with the same lane
+// count, schedule and element rule and H at least the widest position window
+// (see fht::retile_items), with their device copies (uploaded on first use on
+// each device, freed with the last plan that uses them).  `plan.passes[p].items`
+// are for H = min(H, kMaxTarget); plans keep their own items.
+struct ViewProgs {
+    fht::AxisPlan plan;
+    std::mutex mu;
+    std::deque<DevProgs> dev;
+
+    ~ViewProgs()
+    {
+        for (DevProgs &d : dev) {
+            int cur = 0;
+            const bool have = hipGetDevice(&cur) == hipSuccess;
+            (void)hipSetDevice(d.device);
+            if (d.hdrs) (void)hipFree(d.hdrs);
+            if (d.ops) (void)hipFree(d.ops);
+            if (have) (void)hipSetDevice(cur);
+        }
+    }
+
+    fht_status device_progs(const DevProgs **out)
+    {
+        int d = -1;
+        hipError_t e = hipGetDevice(&d);
+        if (e != hipSuccess) return hip_status(e);
+        std::lock_guard<std::mutex> lk(mu);
+        for (const DevProgs &x : dev)
+            if (x.device == d) {
+                *out = &x;
+                return FHT_OK;
+            }
+        std::vector<int32_t> hdrs, ops;
+        for (const fht::Pass &ps : plan.passes) {
+            const int op_base = static_cast<int>(ops.size() / 4);
+            for (size_t i = 0; i < ps.hdrs.size(); i += fht::kHdrInts) {
+                hdrs.insert(hdrs.end(), ps.hdrs.begin() + i, ps.hdrs.begin() + i + fht::kHdrInts);
+                hdrs[hdrs.size() - fht::kHdrInts] += op_base;
+            }
+            ops.insert(ops.end(), ps.ops.begin(), ps.ops.end());
+        }
+        DevProgs x;
+        x.device = d;
+        int32_t *o = nullptr;
+        e = upload(hdrs, &x.hdrs);
+        if (e == hipSuccess) e = upload(ops, &o);
+        x.ops = reinterpret_cast<int4 *>(o);
+        if (e != hipSuccess) {
+            if (x.hdrs) (void)hipFree(x.hdrs);
+            if (o) (void)hipFree(o);
+            return hip_status(e);
+        }
+        dev.push_back(x);
+        *out = &dev.back();
+        return FHT_OK;
+    }
+
+    // First program of pass p in the concatenated tables.
+    int prog_base(size_t p) const
+    {
+        int b = 0;
+        for (size_t i = 0; i < p; ++i) b += static_cast<int>(plan.passes[i].hdrs.size() / fht::kHdrInts);
+        return b;
+    }
+};
+
+struct DevTables {
+    int device = -1;
+    const DevProgs *views[2] = {nullptr, nullptr};
+    std::vector<int32_t *> items;          // per launch
     int32_t *adj[2] = {nullptr, nullptr};  // adjoint tasks per lane view
 };
 
 void free_tables(DevTables &t)
 {
-    if (t.hdrs) (void)hipFree(t.hdrs);
-    if (t.ops) (void)hipFree(t.ops);
     for (int32_t *p : t.adj)
         if (p) (void)hipFree(p);
     for (int32_t *p : t.items)
         if (p) (void)hipFree(p);
     t = DevTables{};
+}
+
+// Process-wide cache of lane-view programs: a view of W lanes is planned once
+// per schedule, element rule and min(H, kMaxTarget).  Bounded by the bytes of
+// the cached host tables, least recently used first out.
+struct AxisKey {
+    int W, H, split, narrow, wide, narrow_w, transition;
+    int s_tile, s_tile_first, first_levels, max_levels, lds_budget, t_tile;
+    bool operator<(const AxisKey &o) const
+    {
+        return std::tie(W, H, split, narrow, wide, narrow_w, transition, s_tile, s_tile_first,
+                        first_levels, max_levels, lds_budget, t_tile) <
+               std::tie(o.W, o.H, o.split, o.narrow, o.wide, o.narrow_w, o.transition, o.s_tile,
+                        o.s_tile_first, o.first_levels, o.max_levels, o.lds_budget, o.t_tile);
+    }
+};
+
+struct AxisCache {
+    std::mutex mu;
+    std::list<std::pair<AxisKey, std::shared_ptr<ViewProgs>>> lru;
+    std::map<AxisKey, decltype(lru)::iterator> index;
+    size_t bytes = 0;
+    size_t capacity = size_t(256) << 20;
+};
+
+AxisCache &axis_cache()
+{
+    // never destroyed: its device tables must not be freed after the HIP
+    // runtime has shut down at process exit
+    static AxisCache *c = new AxisCache;
+    return *c;
+}
+
+size_t table_bytes(const fht::AxisPlan &ax)
+{
+    size_t b = 0;
+    for (const fht::Pass &ps : ax.passes) b += (ps.hdrs.size() + ps.ops.size() + ps.items.size()) * 4;
+    return b;
+}
+
+// The view's programs, and the work items of each pass for height H.
+std::shared_ptr<ViewProgs> plan_view(int W, int H, int split, const fht::ElemRule &rule,
+                                     const fht::Schedule &sc,
+                                     std::vector<std::vector<int32_t>> *items)
+{
+    const int Hk = std::min(H, fht::kMaxTarget);
+    const AxisKey key{W, Hk, split, rule.narrow_bytes, rule.wide_bytes, rule.narrow_width,
+                      rule.transition_bytes, sc.s_tile, sc.s_tile_first, sc.first_levels,
+                      sc.max_levels, sc.lds_budget, sc.t_tile};
+    AxisCache &c = axis_cache();
+    std::shared_ptr<ViewProgs> hit;
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        auto it = c.index.find(key);
+        if (it != c.index.end()) {
+            c.lru.splice(c.lru.begin(), c.lru, it->second);
+            hit = it->second->second;
+        }
+    }
+    if (!hit) {
+        auto made = std::make_shared<ViewProgs>();
+        std::string err;
+        if (!fht::plan_axis(W, Hk, split, rule, sc, &made->plan, &err)) return nullptr;
+        std::lock_guard<std::mutex> lk(c.mu);
+        auto it = c.index.find(key);
+        if (it != c.index.end()) {
+            hit = it->second->second;  // planned meanwhile by another thread
+        } else {
+            hit = made;
+            c.lru.emplace_front(key, hit);
+            c.index[key] = c.lru.begin();
+            c.bytes += table_bytes(hit->plan);
+            while (c.bytes > c.capacity && c.lru.size() > 1) {
+                c.bytes -= table_bytes(c.lru.back().second->plan);
+                c.index.erase(c.lru.back().first);
+                c.lru.pop_back();
+            }
+        }
+    }
+    items->clear();
+    if (H == Hk) {
+        for (const fht::Pass &ps : hit->plan.passes) items->push_back(ps.items);
+    } else {
+        fht::AxisPlan shape;  // passes with programs counted but not copied
+        for (const fht::Pass &ps : hit->plan.passes) {
+            fht::Pass q;
+            q.S = ps.S;
+            q.hdrs.resize(ps.hdrs.size());
+            shape.passes.push_back(std::move(q));
+        }
+        fht::retile_items(&shape, H);
+        for (fht::Pass &ps : shape.passes) items->push_back(std::move(ps.items));
+    }
+    return hit;
 }
 
 }  // namespace
@@ -147,14 +315,14 @@ struct fht_plan_s {
     fht_split split = FHT_SPLIT_S;
     uint32_t qmask = 0;
     int threads = 512, threads_first = 256;
-    fht::AxisPlan axis[2];
+    std::shared_ptr<ViewProgs> view[2];            // programs of lane view v (shared)
+    int vW[2] = {0, 0}, vH[2] = {0, 0};            // lanes and positions of view v
+    std::vector<std::vector<int32_t>> vitems[2];   // work items of view v, pass p
     int npass[4] = {0, 0, 0, 0};
     size_t out_off[4] = {0, 0, 0, 0};
     size_t out_elems = 0;
     size_t ws_off[4][2] = {};
     size_t ws_bytes = 0;
-    std::vector<int32_t> hdrs, ops;  // programs of both views, all passes
-    std::vector<int> prog_base[2];   // first program of view v, pass p
     std::vector<Launch> launches;    // in level order
     fht::AdjointAxis adj[2];         // adjoint steps per lane view (float plans)
     size_t adj_ws_off[4][2] = {};
@@ -186,8 +354,11 @@ struct fht_plan_s {
             }
         DevTables t;
         t.device = d;
-        e = upload(hdrs, &t.hdrs);
-        if (e == hipSuccess) e = upload(ops, &t.ops);
+        for (int v = 0; v < 2; ++v) {
+            if (!view[v]) continue;
+            const fht_status st = view[v]->device_progs(&t.views[v]);
+            if (st != FHT_OK) return st;
+        }
         for (size_t l = 0; e == hipSuccess && l < launches.size(); ++l) {
             int32_t *ptr = nullptr;
             e = upload(launches[l].items, &ptr);
@@ -203,7 +374,9 @@ struct fht_plan_s {
         return FHT_OK;
     }
 
-    bool narrow(int v, size_t p) const { return axis[v].passes[p].max_root_w <= kNarrowWidth; }
+    const fht::AxisPlan &ax(int v) const { return view[v]->plan; }
+
+    bool narrow(int v, size_t p) const { return ax(v).passes[p].max_root_w <= kNarrowWidth; }
 
     // Pass p of lane view v runs both quadrants of the view as pairs: uint8
     // images with both quadrants selected, while the pass keeps 16-bit sums
@@ -220,13 +393,15 @@ struct fht_plan_s {
     // The job of slot r in its pass `level`; workspace offsets are absolute
     // (ws != null) or relative to the workspace (ws == null, batch tables).
     // Pair rows live in the buffers of the pair's positive-slope quadrant.
-    JobDesc job(JobRef r, int level, const void *img, void *out, char *ws, size_t ws_base) const
+    JobDesc job(JobRef r, int level, const void *img, void *out, char *ws, size_t ws_base,
+                const DevProgs *const *progs) const
     {
         JobDesc jd;
         std::memset(&jd, 0, sizeof(jd));
         const int q = r.q, v = q >> 1;
-        const fht::AxisPlan &ax = axis[v];
         const bool final = level == npass[q] - 1;
+        jd.hdrs = progs[v]->hdrs;
+        jd.ops = progs[v]->ops;
         int flags = (v ? fht::JF_COLS : 0) | (final ? fht::JF_FINAL : 0);
         if (r.pair)
             flags |= fht::JF_PAIR;
@@ -254,15 +429,15 @@ struct fht_plan_s {
             jd.dst = ws_ptr(q, level & 1);
             if (!ws) flags |= fht::JF_DST_WS;
         }
-        jd.H = ax.H;
+        jd.H = vH[v];
         jd.ld = C;
         jd.flags = flags;
         return jd;
     }
 };
 
-// A batch's device work list lives in one table blob: jobs, then program
-// headers, then entries, then the items of every launch, each 256-byte aligned.
+// A batch's device work list lives in one table blob: jobs, then the items of
+// every launch, each 256-byte aligned (the programs are the lane views').
 // The blob is built in host memory; it goes to device memory the library
 // allocates (fht_batch_create) or the caller provides (fht_batch_upload).
 struct fht_batch_s {
@@ -270,7 +445,16 @@ struct fht_batch_s {
     int device = -1;
     size_t ws_bytes = 0;
     std::vector<char> blob;
-    size_t off_jobs = 0, off_hdrs = 0, off_ops = 0;
+    size_t off_jobs = 0;
+    struct Pending {            // a job, made when the device is known
+        fht_plan plan;
+        JobRef ref;
+        int level;
+        const void *img;
+        void *out;
+        size_t ws_base;
+    };
+    std::vector<Pending> pending;
     std::vector<size_t> off_items;  // per launch
     char *dev = nullptr;            // device copy of the blob (null until uploaded)
     bool owns = false;              // dev was allocated by the library
@@ -321,10 +505,9 @@ fht_status forward_one(fht_plan plan, const DevTables *t, size_t l, const void *
     fht::PassArgs a;
     std::memset(&a, 0, sizeof(a));
     a.items = reinterpret_cast<const int4 *>(t->items[l]);
-    a.hdrs = t->hdrs;
-    a.ops = reinterpret_cast<const int4 *>(t->ops);
     for (size_t j = 0; j < L.jobs.size(); ++j)
-        a.inl[j] = plan->job(L.jobs[j], L.level, d_img, d_out, static_cast<char *>(d_ws), 0);
+        a.inl[j] = plan->job(L.jobs[j], L.level, d_img, d_out, static_cast<char *>(d_ws), 0,
+                             t->views);
     const int nitems = static_cast<int>(L.items.size() / 4);
     return hip_status(fht::launch_pass(L.combo, a, nitems, L.lds_bytes, L.threads,
                                        static_cast<hipStream_t>(stream)));
@@ -346,8 +529,6 @@ fht_status batch_one(fht_batch batch, size_t l, void *d_ws, void *stream)
     fht::PassArgs a;
     std::memset(&a, 0, sizeof(a));
     a.items = reinterpret_cast<const int4 *>(batch->dev + batch->off_items[l]);
-    a.hdrs = reinterpret_cast<const int32_t *>(batch->dev + batch->off_hdrs);
-    a.ops = reinterpret_cast<const int4 *>(batch->dev + batch->off_ops);
     a.jobs = reinterpret_cast<const JobDesc *>(batch->dev + batch->off_jobs);
     a.ws = static_cast<char *>(d_ws);
     const int nitems = static_cast<int>(L.items.size() / 4);
@@ -372,34 +553,17 @@ bool injected_failure(fht_status *st)
     return false;
 }
 
-// Host half of batch creation: the batch's launches and table blob.
-fht_status batch_prepare(fht_batch_s *b, const fht_plan *plans, int32_t n,
-                         const void *const *d_imgs, void *const *d_outs)
+// Host half of batch creation: the batch's launches and table blob.  The
+// work items go in now; the jobs, which point at each lane view's device
+// programs, are written by finish_jobs once the device is known.
+void batch_prepare(fht_batch_s *b, const fht_plan *plans, int32_t n, const void *const *d_imgs,
+                   void *const *d_outs)
 {
-    // Distinct plans share one copy of their tables.
-    std::vector<fht_plan> uniq;
-    std::vector<int> hdr_base;
-    std::vector<int32_t> hdrs, ops;
-    auto table_of = [&](fht_plan p) {
-        for (size_t u = 0; u < uniq.size(); ++u)
-            if (uniq[u] == p) return static_cast<int>(u);
-        uniq.push_back(p);
-        hdr_base.push_back(static_cast<int>(hdrs.size() / fht::kHdrInts));
-        const int op_base = static_cast<int>(ops.size() / 4);
-        for (size_t i = 0; i < p->hdrs.size(); i += fht::kHdrInts) {
-            hdrs.insert(hdrs.end(), p->hdrs.begin() + i, p->hdrs.begin() + i + fht::kHdrInts);
-            hdrs[hdrs.size() - fht::kHdrInts] += op_base;
-        }
-        ops.insert(ops.end(), p->ops.begin(), p->ops.end());
-        return static_cast<int>(uniq.size() - 1);
-    };
     // Batch launches keyed by (level, combination), in level order.
     std::map<std::pair<int, int>, size_t> key;
-    std::vector<JobDesc> jobs;
     size_t ws = 0;
     for (int i = 0; i < n; ++i) {
         const fht_plan p = plans[i];
-        const int u = table_of(p);
         const size_t ws_base = ws;
         ws += align_up(p->ws_bytes, 256);
         for (const Launch &L : p->launches) {
@@ -413,16 +577,17 @@ fht_status batch_prepare(fht_batch_s *b, const fht_plan *plans, int32_t n,
                 b->launches.back().threads = L.threads;
             }
             Launch &B = b->launches[found->second];
-            std::vector<int> slot;
-            for (const JobRef &r : L.jobs) {
-                slot.push_back(static_cast<int>(jobs.size()));
-                jobs.push_back(p->job(r, L.level, d_imgs[i], d_outs[i], nullptr, ws_base));
-            }
+            const int slot0 = static_cast<int>(b->pending.size());
+            for (const JobRef &r : L.jobs)
+                b->pending.push_back({p, r, L.level, d_imgs[i], d_outs[i], ws_base});
+            const size_t at = B.items.size();
+            B.items.resize(at + L.items.size());
+            int32_t *dst = B.items.data() + at;
             for (size_t k4 = 0; k4 < L.items.size(); k4 += 4) {
-                B.items.push_back(L.items[k4] + hdr_base[u]);
-                B.items.push_back(slot[L.items[k4 + 1]]);
-                B.items.push_back(L.items[k4 + 2]);
-                B.items.push_back(0);
+                dst[k4] = L.items[k4];
+                dst[k4 + 1] = slot0 + L.items[k4 + 1];
+                dst[k4 + 2] = L.items[k4 + 2];
+                dst[k4 + 3] = 0;
             }
             B.lds_bytes = std::max(B.lds_bytes, L.lds_bytes);
         }
@@ -437,20 +602,37 @@ fht_status batch_prepare(fht_batch_s *b, const fht_plan *plans, int32_t n,
         off = align_up(off + bytes, 256);
         return at;
     };
-    b->off_jobs = place(jobs.size() * sizeof(JobDesc));
-    b->off_hdrs = place(hdrs.size() * sizeof(int32_t));
-    b->off_ops = place(ops.size() * sizeof(int32_t));
+    b->off_jobs = place(b->pending.size() * sizeof(JobDesc));
     for (const Launch &L : b->launches) b->off_items.push_back(place(L.items.size() * sizeof(int32_t)));
-    b->blob.assign(std::max<size_t>(off, 256), 0);
-    auto put = [&](size_t at, const void *src, size_t bytes) {
-        if (bytes) std::memcpy(b->blob.data() + at, src, bytes);
-    };
-    put(b->off_jobs, jobs.data(), jobs.size() * sizeof(JobDesc));
-    put(b->off_hdrs, hdrs.data(), hdrs.size() * sizeof(int32_t));
-    put(b->off_ops, ops.data(), ops.size() * sizeof(int32_t));
-    for (size_t l = 0; l < b->launches.size(); ++l)
-        put(b->off_items[l], b->launches[l].items.data(),
-            b->launches[l].items.size() * sizeof(int32_t));
+    b->blob.resize(std::max<size_t>(off, 256));
+    for (size_t l = 0; l < b->launches.size(); ++l) {
+        const std::vector<int32_t> &items = b->launches[l].items;
+        if (!items.empty())
+            std::memcpy(b->blob.data() + b->off_items[l], items.data(), items.size() * sizeof(int32_t));
+    }
+}
+
+// Writes the batch's jobs into its blob for the current device, uploading the
+// lane views' programs there on first use.
+fht_status finish_jobs(fht_batch_s *b)
+{
+    JobDesc *jobs = reinterpret_cast<JobDesc *>(b->blob.data() + b->off_jobs);
+    fht_plan last = nullptr;
+    const DevProgs *progs[2] = {nullptr, nullptr};
+    for (size_t j = 0; j < b->pending.size(); ++j) {
+        const fht_batch_s::Pending &pj = b->pending[j];
+        if (pj.plan != last) {
+            for (int v = 0; v < 2; ++v) {
+                progs[v] = nullptr;
+                if (!pj.plan->view[v]) continue;
+                const fht_status st = pj.plan->view[v]->device_progs(&progs[v]);
+                if (st != FHT_OK) return st;
+            }
+            last = pj.plan;
+        }
+        const JobDesc jd = pj.plan->job(pj.ref, pj.level, pj.img, pj.out, nullptr, pj.ws_base, progs);
+        std::memcpy(jobs + j, &jd, sizeof(jd));
+    }
     return FHT_OK;
 }
 
@@ -524,11 +706,13 @@ fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, fht_dtype 
                 vrule.narrow_bytes = 4;
                 vrule.transition_bytes = 8;
             }
-            std::string err;
-            if (!fht::plan_axis(W, H, static_cast<int>(split), vrule, sc, &p->axis[v], &err)) {
+            p->view[v] = plan_view(W, H, static_cast<int>(split), vrule, sc, &p->vitems[v]);
+            if (!p->view[v]) {
                 delete p;
                 return FHT_EINVAL;
             }
+            p->vW[v] = W;
+            p->vH[v] = H;
         }
         // Output and workspace layout (workspace rows are sized for the widest
         // element type any pass stores).
@@ -536,11 +720,11 @@ fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, fht_dtype 
         int nlevels = 0;
         for (int q = 0; q < 4; ++q) {
             if (!(quadrant_mask & (1u << q))) continue;
-            const fht::AxisPlan &ax = p->axis[q >> 1];
-            const size_t wh = static_cast<size_t>(ax.W) * ax.H;
+            const int v = q >> 1;
+            const size_t wh = static_cast<size_t>(p->vW[v]) * p->vH[v];
             p->out_off[q] = off;
             off += wh;
-            p->npass[q] = static_cast<int>(ax.passes.size());
+            p->npass[q] = static_cast<int>(p->ax(v).passes.size());
             nlevels = std::max(nlevels, p->npass[q]);
             const int nbuf = std::min(p->npass[q] - 1, 2);
             for (int b = 0; b < nbuf; ++b) {
@@ -567,19 +751,6 @@ fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, fht_dtype 
             }
             p->adj_ws_bytes = aws;
         }
-        // Concatenate the program tables of both views.
-        for (int v = 0; v < 2; ++v) {
-            for (const fht::Pass &ps : p->axis[v].passes) {
-                const int op_base = static_cast<int>(p->ops.size() / 4);
-                p->prog_base[v].push_back(static_cast<int>(p->hdrs.size() / fht::kHdrInts));
-                for (size_t i = 0; i < ps.hdrs.size(); i += fht::kHdrInts) {
-                    p->hdrs.insert(p->hdrs.end(), ps.hdrs.begin() + i,
-                                   ps.hdrs.begin() + i + fht::kHdrInts);
-                    p->hdrs[p->hdrs.size() - fht::kHdrInts] += op_base;
-                }
-                p->ops.insert(p->ops.end(), ps.ops.begin(), ps.ops.end());
-            }
-        }
         // Launches: level by level, one per type combination; job slot j of a
         // launch is its j-th quadrant.
         for (int l = 0; l < nlevels; ++l) {
@@ -589,8 +760,10 @@ fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, fht_dtype 
                 const int v = q >> 1;
                 const bool pair = p->pair_pass(v, l);
                 if (pair && (q & 1)) continue;  // run by the pair job of q - 1
-                const fht::Pass &ps = p->axis[v].passes[l];
-                const Combo combo = pass_combo(dtype, p->axis[v], l, pair);
+                const fht::Pass &ps = p->ax(v).passes[l];
+                const std::vector<int32_t> &items = p->vitems[v][l];
+                const int prog_base = p->view[v]->prog_base(l);
+                const Combo combo = pass_combo(dtype, p->ax(v), l, pair);
                 Launch *L = nullptr;
                 for (size_t k : level_launches)
                     if (p->launches[k].combo == combo) L = &p->launches[k];
@@ -605,10 +778,10 @@ fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, fht_dtype 
                 }
                 const int job = static_cast<int>(L->jobs.size());
                 L->jobs.push_back(JobRef{q, pair});
-                for (size_t i = 0; i < ps.items.size(); i += 4) {
-                    L->items.push_back(ps.items[i] + p->prog_base[v][l]);
+                for (size_t i = 0; i < items.size(); i += 4) {
+                    L->items.push_back(items[i] + prog_base);
                     L->items.push_back(job);
-                    L->items.push_back(ps.items[i + 2]);
+                    L->items.push_back(items[i + 2]);
                     L->items.push_back(0);
                 }
                 L->lds_bytes = std::max(L->lds_bytes, ps.max_lds_elems * ps.elem_bytes);
@@ -664,8 +837,7 @@ fht_status fht_plan_launch_info(fht_plan plan, int32_t launch, int32_t *level,
     int64_t bin = 0, bout = 0;
     bool image_counted = false;
     for (const JobRef &r : L.jobs) {
-        const fht::AxisPlan &ax = plan->axis[r.q >> 1];
-        const int64_t wh = static_cast<int64_t>(ax.W) * ax.H;
+        const int64_t wh = static_cast<int64_t>(plan->vW[r.q >> 1]) * plan->vH[r.q >> 1];
         for (int c = 0; c < (r.pair ? 2 : 1); ++c) {
             if (L.level == 0) {
                 // every quadrant of a launch reads the same image; count it once
@@ -749,6 +921,8 @@ fht_status fht_batch_upload(fht_batch batch, void *d_tables, size_t bytes, void 
     if (injected_failure(&st)) return st;
     hipError_t e = hipGetDevice(&batch->device);
     if (e != hipSuccess) return hip_status(e);
+    st = finish_jobs(batch);
+    if (st != FHT_OK) return st;
     e = hipMemcpyAsync(d_tables, batch->blob.data(), batch->blob.size(), hipMemcpyHostToDevice,
                        static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_status(e);
@@ -769,6 +943,13 @@ fht_status fht_batch_create(fht_batch *out, const fht_plan *plans, int32_t n,
     st = fht_batch_prepare(&b, plans, n, d_imgs, d_outs);
     if (st != FHT_OK) return st;
     hipError_t e = hipGetDevice(&b->device);
+    if (e == hipSuccess) {
+        st = finish_jobs(b);
+        if (st != FHT_OK) {
+            delete b;
+            return st;
+        }
+    }
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&b->dev), b->blob.size());
     if (e == hipSuccess) {
         b->owns = true;
@@ -818,15 +999,18 @@ fht_status fht_plan_work(fht_plan plan, int64_t *adds_tree, int64_t *adds_execut
     int64_t tree = 0, done = 0;
     for (int q = 0; q < 4; ++q) {
         if (!(plan->qmask & (1u << q))) continue;
-        const fht::AxisPlan &ax = plan->axis[q >> 1];
+        const int v = q >> 1;
+        const fht::AxisPlan &ax = plan->ax(v);
         // Theorem 1's count: every non-leaf node of width w merges w rows of H
-        const fht::Tree tr = fht::make_tree(ax.W, ax.split);
+        const fht::Tree tr = fht::make_tree(plan->vW[v], ax.split);
         for (const fht::Node &n : tr.nodes)
-            if (n.w > 1) tree += static_cast<int64_t>(n.w) * ax.H;
+            if (n.w > 1) tree += static_cast<int64_t>(n.w) * plan->vH[v];
         // what the kernels add: whole 64-position chunks of every merge entry
-        for (const fht::Pass &ps : ax.passes) {
-            for (size_t i = 0; i < ps.items.size(); i += 4) {
-                const int32_t *h = ps.hdrs.data() + static_cast<size_t>(ps.items[i]) * fht::kHdrInts;
+        for (size_t p = 0; p < ax.passes.size(); ++p) {
+            const fht::Pass &ps = ax.passes[p];
+            const std::vector<int32_t> &items = plan->vitems[v][p];
+            for (size_t i = 0; i < items.size(); i += 4) {
+                const int32_t *h = ps.hdrs.data() + static_cast<size_t>(items[i]) * fht::kHdrInts;
                 int64_t merges = 0;
                 for (int k = 0; k < h[3]; ++k) merges += h[8 + k];
                 done += merges * h[fht::kHdrChunks] * fht::kChunk;
@@ -934,14 +1118,14 @@ fht_status fht_peaks(fht_plan plan, const void *d_out, int32_t k, int32_t radius
     int max_elems = 0;
     for (int q = 0; q < 4; ++q) {
         if (!(plan->qmask & (1u << q))) continue;
-        const fht::AxisPlan &ax = plan->axis[q >> 1];
+        const int v = q >> 1;
         const int j = a.nq++;
         a.src[j] = static_cast<const char *>(d_out) + plan->out_off[q] * eb;
-        a.W[j] = ax.W;
-        a.H[j] = ax.H;
+        a.W[j] = plan->vW[v];
+        a.H[j] = plan->vH[v];
         a.base[j] = plan->out_off[q];
         a.quadrant[j] = q;
-        max_elems = std::max(max_elems, ax.W * ax.H);
+        max_elems = std::max(max_elems, plan->vW[v] * plan->vH[v]);
     }
     a.radius = radius;
     a.min_value = min_value;
@@ -966,7 +1150,7 @@ void fht_debug_fail_next(fht_status code, int32_t count)
 int32_t fht_plan_num_passes(fht_plan plan, int32_t v)
 {
     if (!plan || v < 0 || v > 1 || !(plan->qmask & (3u << (2 * v)))) return -1;
-    return static_cast<int32_t>(plan->axis[v].passes.size());
+    return static_cast<int32_t>(plan->ax(v).passes.size());
 }
 
 fht_status fht_plan_pass_tables(fht_plan plan, int32_t v, int32_t pass, const int32_t **hdrs,
@@ -974,15 +1158,16 @@ fht_status fht_plan_pass_tables(fht_plan plan, int32_t v, int32_t pass, const in
                                 const int32_t **items, int32_t *n_items, int32_t *s_tile)
 {
     if (!plan || v < 0 || v > 1 || !(plan->qmask & (3u << (2 * v)))) return FHT_EINVAL;
-    const fht::AxisPlan &ax = plan->axis[v];
+    const fht::AxisPlan &ax = plan->ax(v);
     if (pass < 0 || pass >= static_cast<int32_t>(ax.passes.size())) return FHT_EINVAL;
     const fht::Pass &ps = ax.passes[pass];
+    const std::vector<int32_t> &its = plan->vitems[v][pass];
     if (hdrs) *hdrs = ps.hdrs.data();
     if (n_progs) *n_progs = static_cast<int32_t>(ps.hdrs.size() / fht::kHdrInts);
     if (ops) *ops = ps.ops.data();
     if (n_ops) *n_ops = static_cast<int32_t>(ps.ops.size() / 4);
-    if (items) *items = ps.items.data();
-    if (n_items) *n_items = static_cast<int32_t>(ps.items.size() / 4);
+    if (items) *items = its.data();
+    if (n_items) *n_items = static_cast<int32_t>(its.size() / 4);
     if (s_tile) *s_tile = ps.S;
     return FHT_OK;
 }

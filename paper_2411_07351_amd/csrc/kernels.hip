@@ -53,6 +53,8 @@ __device__ __forceinline__ JobDesc pick_job(const PassArgs &a, int j)
         d.src = p->src;
         d.dst = p->dst;
         d.dst2 = p->dst2;
+        d.hdrs = p->hdrs;
+        d.ops = p->ops;
         d.H = p->H;
         d.ld = p->ld;
         d.flags = p->flags;
@@ -417,9 +419,9 @@ __global__ void __launch_bounds__(NT) fht_pass_kernel(PassArgs args, int n_items
     const int it = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (it >= n_items) return;
     const E4 item = ld4(as_const(reinterpret_cast<const int32_t *>(args.items)), it);
-    cptr<int32_t> hdr = as_const(args.hdrs) + static_cast<size_t>(item.x) * 32;
     const JobDesc job = pick_job<TABLE>(args, item.y);
-    const int4 *ent = args.ops + hdr[0];
+    cptr<int32_t> hdr = as_const(job.hdrs) + static_cast<size_t>(item.x) * 32;
+    const int4 *ent = job.ops + hdr[0];
 
     const char *src = static_cast<const char *>(job.src);
     if (job.flags & JF_SRC_WS) src = args.ws + reinterpret_cast<uintptr_t>(job.src);

@@ -9,12 +9,14 @@ namespace fht {
 
 // One (image, quadrant or quadrant pair, pass) job of a launch.
 struct JobDesc {
-    const void *src;  // image (first pass) or the previous pass's [W][H] rows
-    void *dst;        // next pass's [W][H] rows or the final output
-    void *dst2;       // pair jobs, final pass: output of the negative-slope quadrant
-    int32_t H;        // positions per lane
-    int32_t ld;       // image row stride in elements (first pass only)
-    int32_t flags;    // JF_* bits
+    const void *src;       // image (first pass) or the previous pass's [W][H] rows
+    void *dst;             // next pass's [W][H] rows or the final output
+    void *dst2;            // pair jobs: rows or output of the negative-slope quadrant
+    const int32_t *hdrs;   // tile-program headers of this job's lane view (32 ints each)
+    const int4 *ops;       // their row entries
+    int32_t H;             // positions per lane
+    int32_t ld;            // image row stride in elements (first pass only)
+    int32_t flags;         // JF_* bits
     int32_t pad;
 };
 
@@ -31,9 +33,7 @@ enum : int32_t {
 constexpr int kInlineJobs = 4;
 
 struct PassArgs {
-    const int4 *items;     // {program, job, first position, 0}
-    const int32_t *hdrs;   // 32 ints per program
-    const int4 *ops;       // row operations
+    const int4 *items;     // {program of the job's view, job, first position, 0}
     const JobDesc *jobs;   // device job table, or null to use inl
     char *ws;              // workspace base for JF_*_WS offsets
     JobDesc inl[kInlineJobs];

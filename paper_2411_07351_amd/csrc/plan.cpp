@@ -372,6 +372,24 @@ bool plan_axis(int W, int H, int split, const ElemRule &rule, const Schedule &sc
     return true;
 }
 
+void retile_items(AxisPlan *ax, int H)
+{
+    ax->H = H;
+    for (Pass &ps : ax->passes) {
+        const int nprog = static_cast<int>(ps.hdrs.size() / kHdrInts);
+        ps.items.clear();
+        ps.items.reserve(static_cast<size_t>(nprog) * ((H + ps.S - 1) / ps.S) * 4);
+        for (int prog = 0; prog < nprog; ++prog) {
+            for (int s0 = 0; s0 < H; s0 += ps.S) {
+                ps.items.push_back(prog);
+                ps.items.push_back(0);
+                ps.items.push_back(s0);
+                ps.items.push_back(0);
+            }
+        }
+    }
+}
+
 // Adjoint steps.  The forward merge of a node of width w into children of
 // widths w0, w1 is J[t] = J0[t0(t)] + Rotate(J1[t1(t)], t - t1(t)); its adjoint
 // gives left-child row u the sum of the parent rows t with t0(t) = u, and

@@ -94,6 +94,12 @@ struct ElemRule {
 bool plan_axis(int W, int H, int split, const ElemRule &rule, const Schedule &sched,
                AxisPlan *out, std::string *err);
 
+// Tile programs depend on H only through the position tile, which is
+// min(H, a width fixed by the schedule and the slope tiles) <= kMaxTarget: a
+// plan made for any H >= kMaxTarget serves every such H once its work items
+// are regenerated.  Moves `ax` to height H >= kMaxTarget.
+void retile_items(AxisPlan *ax, int H);
+
 // Gather steps of the adjoint (back-projection) of Alg. 1, top down.  Step k
 // takes the gradients of the frontier of level L - k (L = root height) to
 // those of level L - k - 1; in every step, output row x is
