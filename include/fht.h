@@ -158,6 +158,18 @@ fht_status fht_plan_upload(fht_plan plan);
  */
 fht_status fht_forward(fht_plan plan, const void *d_img, void *d_out, void *d_ws, void *stream);
 
+/*
+ * fht_forward for n same-shape images at once (one launch per fused pass for
+ * all of them): image b is read at d_imgs + b * img_stride and its output
+ * written at d_outs + b * out_stride (strides in bytes, >= 0, multiples of
+ * the element sizes).  d_ws holds fht_plan_workspace_bytes_many(plan, n)
+ * bytes.  n in 1..65535.  Errors: as fht_forward, FHT_EINVAL for bad n or
+ * strides.
+ */
+size_t fht_plan_workspace_bytes_many(fht_plan plan, int32_t n);
+fht_status fht_forward_many(fht_plan plan, int32_t n, const void *d_imgs, int64_t img_stride,
+                            void *d_outs, int64_t out_stride, void *d_ws, void *stream);
+
 /* Enqueues only launch `launch` (0 <= launch < fht_plan_num_launches) of
  * fht_forward, with the same arguments.  Running launches 0, 1, ... in order
  * on one stream equals fht_forward; it lets a caller time or interleave the
@@ -232,6 +244,13 @@ size_t fht_plan_adjoint_workspace_bytes(fht_plan plan);
 fht_status fht_plan_adjoint_tasks(fht_plan plan, int32_t v, const int32_t **tasks,
                                   int32_t *levels, int32_t *lanes);
 fht_status fht_adjoint(fht_plan plan, const void *d_gout, void *d_gimg, void *d_ws, void *stream);
+/* fht_adjoint for n same-shape images: output gradient b at d_gouts +
+ * b * gout_stride, image gradient b at d_gimgs + b * gimg_stride (bytes);
+ * d_ws holds fht_plan_adjoint_workspace_bytes_many(plan, n) bytes.  n in
+ * 1..65535.  Errors: as fht_adjoint. */
+size_t fht_plan_adjoint_workspace_bytes_many(fht_plan plan, int32_t n);
+fht_status fht_adjoint_many(fht_plan plan, int32_t n, const void *d_gouts, int64_t gout_stride,
+                            void *d_gimgs, int64_t gimg_stride, void *d_ws, void *stream);
 
 /*
  * Peak finding on the quadrant outputs of one image (the step after the
@@ -260,7 +279,8 @@ fht_status fht_peaks(fht_plan plan, const void *d_out, int32_t k, int32_t radius
 
 /*
  * Fault injection for tests of error handling: the next `count` calls that
- * enqueue device work (fht_forward, fht_forward_launch, fht_adjoint, fht_peaks,
+ * enqueue device work (fht_forward, fht_forward_many, fht_forward_launch,
+ * fht_adjoint, fht_adjoint_many, fht_peaks,
  * fht_batch_upload, fht_batch_run, fht_batch_run_launch) return `code` after checking their
  * arguments and before enqueuing anything.  count <= 0 or code == FHT_OK
  * disarms it.  Process-wide; safe to call from any thread.

@@ -36,7 +36,8 @@ __all__ = [
     "fht_batch_prepare", "fht_batch_tables_bytes", "fht_batch_upload", "fht_debug_fail_next",
     "fht_plan_adjoint_workspace_bytes", "fht_plan_adjoint_tasks", "fht_adjoint",
     "HoughFunction", "hough_autograd", "fht_peaks_workspace_bytes", "fht_peaks", "PEAK_DTYPE",
-    "fht_plan_work", "fht_plan_launch_kernel",
+    "fht_plan_work", "fht_plan_launch_kernel", "fht_plan_workspace_bytes_many",
+    "fht_forward_many", "fht_plan_adjoint_workspace_bytes_many", "fht_adjoint_many",
 ]
 
 FHT_U8, FHT_F32, FHT_F64 = 0, 1, 2
@@ -56,6 +57,8 @@ EXPORTED = (
     "fht_batch_prepare", "fht_batch_tables_bytes", "fht_batch_upload", "fht_debug_fail_next",
     "fht_plan_adjoint_workspace_bytes", "fht_plan_adjoint_tasks", "fht_adjoint",
     "fht_peaks_workspace_bytes", "fht_peaks", "fht_plan_work", "fht_plan_launch_kernel",
+    "fht_plan_workspace_bytes_many", "fht_forward_many", "fht_plan_adjoint_workspace_bytes_many",
+    "fht_adjoint_many",
 )
 
 # struct fht_peak
@@ -95,6 +98,10 @@ _sig("fht_plan_launch_info", _i32, _vp, _i32, _pi32, ctypes.POINTER(_i64),
      ctypes.POINTER(_i64), _pi32)
 _sig("fht_plan_work", _i32, _vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64))
 _sig("fht_plan_launch_kernel", ctypes.c_char_p, _vp, _i32)
+_sig("fht_plan_workspace_bytes_many", _sz, _vp, _i32)
+_sig("fht_forward_many", _i32, _vp, _i32, _vp, _i64, _vp, _i64, _vp, _vp)
+_sig("fht_plan_adjoint_workspace_bytes_many", _sz, _vp, _i32)
+_sig("fht_adjoint_many", _i32, _vp, _i32, _vp, _i64, _vp, _i64, _vp, _vp)
 _sig("fht_plan_upload", _i32, _vp)
 _sig("fht_forward", _i32, _vp, _vp, _vp, _vp, _vp)
 _sig("fht_forward_launch", _i32, _vp, _i32, _vp, _vp, _vp, _vp)
@@ -194,6 +201,26 @@ def fht_plan_upload(plan: int) -> None:
 
 def fht_forward(plan: int, d_img: int, d_out: int, d_ws: int | None, stream: int | None) -> None:
     _check(_lib.fht_forward(plan, d_img, d_out, d_ws, stream), "fht_forward")
+
+
+def fht_plan_workspace_bytes_many(plan: int, n: int) -> int:
+    return _lib.fht_plan_workspace_bytes_many(plan, n)
+
+
+def fht_forward_many(plan: int, n: int, d_imgs: int, img_stride: int, d_outs: int,
+                     out_stride: int, d_ws: int | None, stream: int | None) -> None:
+    _check(_lib.fht_forward_many(plan, n, d_imgs, img_stride, d_outs, out_stride, d_ws, stream),
+           "fht_forward_many")
+
+
+def fht_plan_adjoint_workspace_bytes_many(plan: int, n: int) -> int:
+    return _lib.fht_plan_adjoint_workspace_bytes_many(plan, n)
+
+
+def fht_adjoint_many(plan: int, n: int, d_gouts: int, gout_stride: int, d_gimgs: int,
+                     gimg_stride: int, d_ws: int | None, stream: int | None) -> None:
+    _check(_lib.fht_adjoint_many(plan, n, d_gouts, gout_stride, d_gimgs, gimg_stride, d_ws,
+                                 stream), "fht_adjoint_many")
 
 
 def fht_forward_launch(plan: int, launch: int, d_img: int, d_out: int, d_ws: int | None,
@@ -417,6 +444,45 @@ class Plan:
         return gimg
 
 
+    def forward_many(self, imgs, outs=None, ws=None, stream=None):
+        """Forward transform of a same-shape batch imgs (n x rows x cols,
+        contiguous): returns outs (n x out_elems), one launch per pass for all."""
+        torch = _torch()
+        if not imgs.is_cuda or not imgs.is_contiguous() or imgs.dim() != 3 \
+                or tuple(imgs.shape[1:]) != (self.rows, self.cols) or imgs.dtype != self.in_dtype:
+            raise ValueError(f"images must be contiguous {self.in_dtype} of shape "
+                             f"(n, {self.rows}, {self.cols}) on the device")
+        n = imgs.shape[0]
+        if outs is None:
+            outs = torch.empty((n, self.out_elems), dtype=self.out_dtype, device=imgs.device)
+        if outs.shape != (n, self.out_elems) or outs.dtype != self.out_dtype or not outs.is_contiguous():
+            raise ValueError("outputs must be a contiguous (n, out_elems) tensor of the output dtype")
+        wbytes = fht_plan_workspace_bytes_many(self.handle, n)
+        if ws is None and wbytes:
+            ws = torch.empty(wbytes, dtype=torch.uint8, device=imgs.device)
+        fht_forward_many(self.handle, n, imgs.data_ptr(), imgs.stride(0) * imgs.element_size(),
+                         outs.data_ptr(), outs.stride(0) * outs.element_size(),
+                         ws.data_ptr() if ws is not None else None, _stream_handle(stream))
+        return outs
+
+    def adjoint_many(self, gouts, gimgs=None, ws=None, stream=None):
+        """Image gradients (n x rows x cols) for output gradients gouts
+        (n x out_elems, contiguous; float plans only)."""
+        torch = _torch()
+        if not gouts.is_cuda or not gouts.is_contiguous() or gouts.dim() != 2 \
+                or gouts.shape[1] != self.out_elems or gouts.dtype != self.out_dtype:
+            raise ValueError("output gradients must be a contiguous (n, out_elems) device tensor")
+        n = gouts.shape[0]
+        if gimgs is None:
+            gimgs = torch.empty((n, self.rows, self.cols), dtype=self.in_dtype, device=gouts.device)
+        wbytes = fht_plan_adjoint_workspace_bytes_many(self.handle, n)
+        if ws is None and wbytes:
+            ws = torch.empty(wbytes, dtype=torch.uint8, device=gouts.device)
+        fht_adjoint_many(self.handle, n, gouts.data_ptr(), gouts.stride(0) * gouts.element_size(),
+                         gimgs.data_ptr(), gimgs.stride(0) * gimgs.element_size(),
+                         ws.data_ptr() if ws is not None else None, _stream_handle(stream))
+        return gimgs
+
     def peaks(self, out, k: int = 32, radius: int = 3, min_value: float = 0.0,
               capacity: int = 1 << 16, stream=None):
         """The k strongest local maxima of the output `out` (see fht_peaks):
@@ -437,30 +503,48 @@ class Plan:
 
 
 class HoughFunction(torch.autograd.Function):
-    """Differentiable forward transform of one float image: returns the flat
-    output (all quadrants); the backward pass is the library's adjoint."""
+    """Differentiable forward transform of one float image (rows x cols) or a
+    batch of same-shape images (n x rows x cols): returns the flat output (all
+    quadrants; n x out_elems for a batch); the backward pass is the library's
+    adjoint (``fht_adjoint`` / ``fht_adjoint_many``)."""
 
     @staticmethod
     def forward(ctx, img, plan):
-        out = plan.new_out(img.device)
-        plan.forward(img.contiguous(), out)
         ctx.plan = plan
-        return out
+        img = img.contiguous()
+        if img.dim() == 2:
+            out = plan.new_out(img.device)
+            plan.forward(img, out)
+            return out
+        return plan.forward_many(img)
 
     @staticmethod
     def backward(ctx, gout):
-        return ctx.plan.adjoint(gout.contiguous()), None
+        gout = gout.contiguous()
+        if gout.dim() == 1:
+            return ctx.plan.adjoint(gout), None
+        return ctx.plan.adjoint_many(gout), None
 
 
 def hough_autograd(img, split="S", quadrants=(0, 1, 2, 3)) -> list:
-    """`hough` with gradients: one (W, H) tensor per quadrant, views of one
-    flat output whose backward runs ``fht_adjoint``."""
-    key = (tuple(img.shape), img.dtype, _split_code(split), tuple(quadrants))
+    """`hough` with gradients for one image (rows x cols) or a same-shape batch
+    (n x rows x cols): one tensor per quadrant, (W, H) or (n, W, H), views of
+    one flat output whose backward runs the library's adjoint."""
+    shape = tuple(img.shape[-2:])
+    key = (shape, img.dtype, _split_code(split), tuple(quadrants))
     plan = _plan_cache.get(key)
     if plan is None:
-        plan = Plan(img.shape[0], img.shape[1], img.dtype, split, quadrants)
+        plan = Plan(shape[0], shape[1], img.dtype, split, quadrants)
         _plan_cache[key] = plan
-    return plan.split_out(HoughFunction.apply(img, plan))
+    out = HoughFunction.apply(img, plan)
+    if img.dim() == 2:
+        return plan.split_out(out)
+    res = []
+    for q in plan.quadrants:
+        W, H = plan.shapes[q]
+        off = plan.offsets[q]
+        res.append(out[:, off:off + W * H].view(-1, W, H))
+    return res
 
 
 class Batch:

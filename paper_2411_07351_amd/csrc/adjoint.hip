@@ -32,8 +32,10 @@ __global__ void __launch_bounds__(256) adj_step_kernel(AdjArgs args)
     const int n = __builtin_amdgcn_readfirstlane(task.y);
     const int r0 = __builtin_amdgcn_readfirstlane(task.z);
     const bool right = __builtin_amdgcn_readfirstlane(task.w) != 0;
-    const T *src = static_cast<const T *>(job.src);
-    T *dst = static_cast<T *>(job.dst) + static_cast<size_t>(x) * H;
+    const int64_t b = blockIdx.z;  // image of a same-shape batch
+    const T *src = reinterpret_cast<const T *>(static_cast<const char *>(job.src) + b * args.src_stride);
+    T *dst = reinterpret_cast<T *>(static_cast<char *>(job.dst) + b * args.dst_stride) +
+             static_cast<size_t>(x) * H;
     const bool mirror = job.mirror_in != 0;
     for (int s0 = 0; s0 < H; s0 += 256) {
         T acc[4] = {T(0), T(0), T(0), T(0)};
@@ -76,8 +78,11 @@ __global__ void __launch_bounds__(256) adj_combine_kernel(CombineArgs args)
 #pragma unroll
     for (int k = 0; k < kTile / 4; ++k) acc[k] = T(0);
     const int j = j0 + tj;
+    const int64_t b = blockIdx.z;  // image of a same-shape batch
     for (int q = 0; q < 2; ++q) {
-        const T *g = static_cast<const T *>(args.src[q]);
+        const T *g = args.src[q] ? reinterpret_cast<const T *>(static_cast<const char *>(args.src[q]) +
+                                                               b * args.src_stride[q])
+                                 : nullptr;
         if (!g || j >= C) continue;
         const int jj = (args.mirror[q] && j != 0) ? C - j : j;
 #pragma unroll
@@ -87,7 +92,9 @@ __global__ void __launch_bounds__(256) adj_combine_kernel(CombineArgs args)
         }
     }
     for (int q = 2; q < 4; ++q) {
-        const T *g = static_cast<const T *>(args.src[q]);
+        const T *g = args.src[q] ? reinterpret_cast<const T *>(static_cast<const char *>(args.src[q]) +
+                                                               b * args.src_stride[q])
+                                 : nullptr;
         if (!g) continue;  // uniform across the block
         // stage g[j0 + a][i'(i0 + b)] as tile[a][b], threads along b
         const int b = threadIdx.x & 63;
@@ -102,7 +109,7 @@ __global__ void __launch_bounds__(256) adj_combine_kernel(CombineArgs args)
         for (int k = 0; k < kTile / 4; ++k) acc[k] += tile[tj][ti + 4 * k];
         __syncthreads();
     }
-    T *out = static_cast<T *>(args.dst);
+    T *out = reinterpret_cast<T *>(static_cast<char *>(args.dst) + b * args.dst_stride);
     if (j < C) {
 #pragma unroll
         for (int k = 0; k < kTile / 4; ++k) {
@@ -115,10 +122,10 @@ __global__ void __launch_bounds__(256) adj_combine_kernel(CombineArgs args)
 }  // namespace
 
 hipError_t launch_adjoint_step(Real real, const AdjArgs &args, int n_jobs, int max_w,
-                               hipStream_t stream)
+                               hipStream_t stream, int n_images)
 {
-    if (n_jobs <= 0 || max_w <= 0) return hipSuccess;
-    const dim3 grid((max_w + kRowsPerBlock - 1) / kRowsPerBlock, n_jobs), block(256);
+    if (n_jobs <= 0 || max_w <= 0 || n_images <= 0) return hipSuccess;
+    const dim3 grid((max_w + kRowsPerBlock - 1) / kRowsPerBlock, n_jobs, n_images), block(256);
     if (real == Real::F64)
         adj_step_kernel<double><<<grid, block, 0, stream>>>(args);
     else
@@ -126,9 +133,12 @@ hipError_t launch_adjoint_step(Real real, const AdjArgs &args, int n_jobs, int m
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_combine(Real real, const CombineArgs &args, hipStream_t stream)
+hipError_t launch_adjoint_combine(Real real, const CombineArgs &args, hipStream_t stream,
+                                  int n_images)
 {
-    const dim3 grid((args.C + kTile - 1) / kTile, (args.R + kTile - 1) / kTile), block(256);
+    if (n_images <= 0) return hipSuccess;
+    const dim3 grid((args.C + kTile - 1) / kTile, (args.R + kTile - 1) / kTile, n_images),
+        block(256);
     if (real == Real::F64)
         adj_combine_kernel<double><<<grid, block, 0, stream>>>(args);
     else

@@ -498,19 +498,24 @@ fht_status make_schedule(const fht_schedule *sched, fht::Schedule *sc)
     return FHT_OK;
 }
 
+// Launch l of the plan for n same-shape images (image b at b strides, in bytes).
 fht_status forward_one(fht_plan plan, const DevTables *t, size_t l, const void *d_img,
-                       void *d_out, void *d_ws, void *stream)
+                       void *d_out, void *d_ws, void *stream, int n = 1, int64_t img_stride = 0,
+                       int64_t out_stride = 0)
 {
     const Launch &L = plan->launches[l];
     fht::PassArgs a;
     std::memset(&a, 0, sizeof(a));
     a.items = reinterpret_cast<const int4 *>(t->items[l]);
+    a.img_stride = img_stride;
+    a.out_stride = out_stride;
+    a.ws_stride = static_cast<int64_t>(align_up(plan->ws_bytes, 256));
     for (size_t j = 0; j < L.jobs.size(); ++j)
         a.inl[j] = plan->job(L.jobs[j], L.level, d_img, d_out, static_cast<char *>(d_ws), 0,
                              t->views);
     const int nitems = static_cast<int>(L.items.size() / 4);
     return hip_status(fht::launch_pass(L.combo, a, nitems, L.lds_bytes, L.threads,
-                                       static_cast<hipStream_t>(stream)));
+                                       static_cast<hipStream_t>(stream), n));
 }
 
 fht_status forward_checks(fht_plan plan, const void *d_img, void *d_out, void *d_ws,
@@ -881,6 +886,24 @@ fht_status fht_forward(fht_plan plan, const void *d_img, void *d_out, void *d_ws
     return st;
 }
 
+size_t fht_plan_workspace_bytes_many(fht_plan plan, int32_t n)
+{
+    if (!plan || n < 1) return 0;
+    return plan->ws_bytes ? static_cast<size_t>(n) * align_up(plan->ws_bytes, 256) : 0;
+}
+
+fht_status fht_forward_many(fht_plan plan, int32_t n, const void *d_imgs, int64_t img_stride,
+                            void *d_outs, int64_t out_stride, void *d_ws, void *stream)
+{
+    if (n < 1 || n > 65535 || img_stride < 0 || out_stride < 0) return FHT_EINVAL;
+    const DevTables *t = nullptr;
+    fht_status st = forward_checks(plan, d_imgs, d_outs, d_ws, &t);
+    if (st == FHT_OK && injected_failure(&st)) return st;
+    for (size_t l = 0; st == FHT_OK && l < plan->launches.size(); ++l)
+        st = forward_one(plan, t, l, d_imgs, d_outs, d_ws, stream, n, img_stride, out_stride);
+    return st;
+}
+
 fht_status fht_forward_launch(fht_plan plan, int32_t launch, const void *d_img, void *d_out,
                               void *d_ws, void *stream)
 {
@@ -1036,9 +1059,17 @@ fht_status fht_plan_adjoint_tasks(fht_plan plan, int32_t v, const int32_t **task
     return FHT_OK;
 }
 
-fht_status fht_adjoint(fht_plan plan, const void *d_gout, void *d_gimg, void *d_ws, void *stream)
+size_t fht_plan_adjoint_workspace_bytes_many(fht_plan plan, int32_t n)
 {
-    if (!plan || !d_gout || !d_gimg) return FHT_EINVAL;
+    if (!plan || n < 1) return 0;
+    return plan->adj_ws_bytes ? static_cast<size_t>(n) * align_up(plan->adj_ws_bytes, 256) : 0;
+}
+
+fht_status fht_adjoint_many(fht_plan plan, int32_t n, const void *d_gouts, int64_t gout_stride,
+                            void *d_gimgs, int64_t gimg_stride, void *d_ws, void *stream)
+{
+    if (!plan || !d_gouts || !d_gimgs) return FHT_EINVAL;
+    if (n < 1 || n > 65535 || gout_stride < 0 || gimg_stride < 0) return FHT_EINVAL;
     if (plan->dtype == FHT_U8) return FHT_EDTYPE;
     if (plan->adj_ws_bytes && !d_ws) return FHT_EINVAL;
     int ndev = 0;
@@ -1049,15 +1080,18 @@ fht_status fht_adjoint(fht_plan plan, const void *d_gout, void *d_gimg, void *d_
     if (injected_failure(&st)) return st;
     const fht::Real real = plan->dtype == FHT_F64 ? fht::Real::F64 : fht::Real::F32;
     const size_t eb = acc_bytes(plan->dtype);
+    const int64_t ws_stride = static_cast<int64_t>(align_up(plan->adj_ws_bytes, 256));
     hipStream_t hs = static_cast<hipStream_t>(stream);
     char *ws = static_cast<char *>(d_ws);
-    const char *gout = static_cast<const char *>(d_gout);
+    const char *gout = static_cast<const char *>(d_gouts);
     int max_levels = 0;
     for (int q = 0; q < 4; ++q)
         if (plan->qmask & (1u << q)) max_levels = std::max(max_levels, plan->adj[q >> 1].levels);
     for (int k = 0; k < max_levels; ++k) {
         fht::AdjArgs a;
         std::memset(&a, 0, sizeof(a));
+        a.src_stride = k == 0 ? gout_stride : ws_stride;
+        a.dst_stride = ws_stride;
         int nj = 0, max_w = 0;
         for (int q = 0; q < 4; ++q) {
             if (!(plan->qmask & (1u << q))) continue;
@@ -1074,23 +1108,30 @@ fht_status fht_adjoint(fht_plan plan, const void *d_gout, void *d_gimg, void *d_
             j.mirror_in = (k == 0 && (q & 1)) ? 1 : 0;
             max_w = std::max(max_w, ax.W);
         }
-        const hipError_t e = fht::launch_adjoint_step(real, a, nj, max_w, hs);
+        const hipError_t e = fht::launch_adjoint_step(real, a, nj, max_w, hs, n);
         if (e != hipSuccess) return hip_status(e);
     }
     fht::CombineArgs c;
     std::memset(&c, 0, sizeof(c));
     c.R = plan->R;
     c.C = plan->C;
-    c.dst = d_gimg;
+    c.dst = d_gimgs;
+    c.dst_stride = gimg_stride;
     for (int q = 0; q < 4; ++q) {
         if (!(plan->qmask & (1u << q))) continue;
         const int L = plan->adj[q >> 1].levels;
         // after the steps a negative-slope quadrant is in the mirrored frame
         c.src[q] = L > 0 ? static_cast<const void *>(ws + plan->adj_ws_off[q][(L - 1) & 1])
                          : static_cast<const void *>(gout + plan->out_off[q] * eb);
+        c.src_stride[q] = L > 0 ? ws_stride : gout_stride;
         c.mirror[q] = (L > 0 && (q & 1)) ? 1 : 0;
     }
-    return hip_status(fht::launch_adjoint_combine(real, c, hs));
+    return hip_status(fht::launch_adjoint_combine(real, c, hs, n));
+}
+
+fht_status fht_adjoint(fht_plan plan, const void *d_gout, void *d_gimg, void *d_ws, void *stream)
+{
+    return fht_adjoint_many(plan, 1, d_gout, 0, d_gimg, 0, d_ws, stream);
 }
 
 size_t fht_peaks_workspace_bytes(int32_t capacity)

@@ -431,6 +431,14 @@ __global__ void __launch_bounds__(NT) fht_pass_kernel(PassArgs args, int n_items
         dst = args.ws + reinterpret_cast<uintptr_t>(job.dst);
         dst2 = args.ws + reinterpret_cast<uintptr_t>(job.dst2);
     }
+    if constexpr (!TABLE) {
+        // image blockIdx.y of a same-shape batch
+        const int64_t b = blockIdx.y;
+        src += b * (FROM_IMAGE ? args.img_stride : args.ws_stride);
+        const int64_t od = b * ((job.flags & JF_FINAL) ? args.out_stride : args.ws_stride);
+        dst += od;
+        dst2 += od;
+    }
 
     switch (hdr[26]) {
     case 1: run_item<NT, 1, TSrc, TL, TD, FROM_IMAGE, PAIR>(lds, hdr, ent, job, src, dst, dst2, item.z); break;
@@ -441,9 +449,10 @@ __global__ void __launch_bounds__(NT) fht_pass_kernel(PassArgs args, int n_items
 }
 
 template <int NT, typename TSrc, typename TL, typename TD, bool FROM_IMAGE, bool PAIR>
-hipError_t launch_nt(const PassArgs &args, int n_items, int lds_bytes, hipStream_t stream)
+hipError_t launch_nt(const PassArgs &args, int n_items, int lds_bytes, hipStream_t stream,
+                     int n_images)
 {
-    const dim3 grid((n_items + 7) / 8 * 8), block(NT);
+    const dim3 grid((n_items + 7) / 8 * 8, n_images), block(NT);
     if (args.jobs)
         fht_pass_kernel<NT, TSrc, TL, TD, FROM_IMAGE, true, PAIR><<<grid, block, lds_bytes, stream>>>(args, n_items);
     else
@@ -453,35 +462,37 @@ hipError_t launch_nt(const PassArgs &args, int n_items, int lds_bytes, hipStream
 
 template <typename TSrc, typename TL, typename TD, bool FROM_IMAGE, bool PAIR = false>
 hipError_t launch_typed(const PassArgs &args, int n_items, int lds_bytes, int threads,
-                        hipStream_t stream)
+                        hipStream_t stream, int n_images)
 {
     if (threads == 512)
-        return launch_nt<512, TSrc, TL, TD, FROM_IMAGE, PAIR>(args, n_items, lds_bytes, stream);
-    return launch_nt<256, TSrc, TL, TD, FROM_IMAGE, PAIR>(args, n_items, lds_bytes, stream);
+        return launch_nt<512, TSrc, TL, TD, FROM_IMAGE, PAIR>(args, n_items, lds_bytes, stream,
+                                                              n_images);
+    return launch_nt<256, TSrc, TL, TD, FROM_IMAGE, PAIR>(args, n_items, lds_bytes, stream,
+                                                          n_images);
 }
 
 }  // namespace
 
 hipError_t launch_pass(Combo combo, const PassArgs &args, int n, int lds, int threads,
-                       hipStream_t stream)
+                       hipStream_t stream, int n_images)
 {
-    if (n <= 0) return hipSuccess;
+    if (n <= 0 || n_images <= 0) return hipSuccess;
     switch (combo) {
-    case Combo::U8_U16_U16: return launch_typed<uint8_t, uint16_t, uint16_t, true>(args, n, lds, threads, stream);
-    case Combo::U8_U16_I32: return launch_typed<uint8_t, uint16_t, int32_t, true>(args, n, lds, threads, stream);
-    case Combo::U16_U16_U16: return launch_typed<uint16_t, uint16_t, uint16_t, false>(args, n, lds, threads, stream);
-    case Combo::U16_U16_I32: return launch_typed<uint16_t, uint16_t, int32_t, false>(args, n, lds, threads, stream);
-    case Combo::U16_I32_I32: return launch_typed<uint16_t, int32_t, int32_t, false>(args, n, lds, threads, stream);
-    case Combo::I32_I32_I32: return launch_typed<int32_t, int32_t, int32_t, false>(args, n, lds, threads, stream);
-    case Combo::F32_FIRST: return launch_typed<float, float, float, true>(args, n, lds, threads, stream);
-    case Combo::F32_LATER: return launch_typed<float, float, float, false>(args, n, lds, threads, stream);
-    case Combo::F64_FIRST: return launch_typed<double, double, double, true>(args, n, lds, threads, stream);
-    case Combo::F64_LATER: return launch_typed<double, double, double, false>(args, n, lds, threads, stream);
-    case Combo::P_U8_FIRST: return launch_typed<uint8_t, uint32_t, uint32_t, true, true>(args, n, lds, threads, stream);
-    case Combo::P_U8_FIRST_FINAL: return launch_typed<uint8_t, uint32_t, int32_t, true, true>(args, n, lds, threads, stream);
-    case Combo::P_U16_MID: return launch_typed<uint32_t, uint32_t, uint32_t, false, true>(args, n, lds, threads, stream);
-    case Combo::P_U16_MID_FINAL: return launch_typed<uint32_t, uint32_t, int32_t, false, true>(args, n, lds, threads, stream);
-    case Combo::P_I32: return launch_typed<uint32_t, uint2, int32_t, false, true>(args, n, lds, threads, stream);
+    case Combo::U8_U16_U16: return launch_typed<uint8_t, uint16_t, uint16_t, true>(args, n, lds, threads, stream, n_images);
+    case Combo::U8_U16_I32: return launch_typed<uint8_t, uint16_t, int32_t, true>(args, n, lds, threads, stream, n_images);
+    case Combo::U16_U16_U16: return launch_typed<uint16_t, uint16_t, uint16_t, false>(args, n, lds, threads, stream, n_images);
+    case Combo::U16_U16_I32: return launch_typed<uint16_t, uint16_t, int32_t, false>(args, n, lds, threads, stream, n_images);
+    case Combo::U16_I32_I32: return launch_typed<uint16_t, int32_t, int32_t, false>(args, n, lds, threads, stream, n_images);
+    case Combo::I32_I32_I32: return launch_typed<int32_t, int32_t, int32_t, false>(args, n, lds, threads, stream, n_images);
+    case Combo::F32_FIRST: return launch_typed<float, float, float, true>(args, n, lds, threads, stream, n_images);
+    case Combo::F32_LATER: return launch_typed<float, float, float, false>(args, n, lds, threads, stream, n_images);
+    case Combo::F64_FIRST: return launch_typed<double, double, double, true>(args, n, lds, threads, stream, n_images);
+    case Combo::F64_LATER: return launch_typed<double, double, double, false>(args, n, lds, threads, stream, n_images);
+    case Combo::P_U8_FIRST: return launch_typed<uint8_t, uint32_t, uint32_t, true, true>(args, n, lds, threads, stream, n_images);
+    case Combo::P_U8_FIRST_FINAL: return launch_typed<uint8_t, uint32_t, int32_t, true, true>(args, n, lds, threads, stream, n_images);
+    case Combo::P_U16_MID: return launch_typed<uint32_t, uint32_t, uint32_t, false, true>(args, n, lds, threads, stream, n_images);
+    case Combo::P_U16_MID_FINAL: return launch_typed<uint32_t, uint32_t, int32_t, false, true>(args, n, lds, threads, stream, n_images);
+    case Combo::P_I32: return launch_typed<uint32_t, uint2, int32_t, false, true>(args, n, lds, threads, stream, n_images);
     }
     return hipErrorInvalidValue;
 }

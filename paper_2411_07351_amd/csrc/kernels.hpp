@@ -36,6 +36,9 @@ struct PassArgs {
     const int4 *items;     // {program of the job's view, job, first position, 0}
     const JobDesc *jobs;   // device job table, or null to use inl
     char *ws;              // workspace base for JF_*_WS offsets
+    // Same-shape image batches (grid.y = image b, inline jobs only): image b's
+    // image, output and workspace sit b strides (bytes) after image 0's.
+    int64_t img_stride, out_stride, ws_stride;
     JobDesc inl[kInlineJobs];
 };
 
@@ -67,9 +70,10 @@ enum class Combo {
 };
 
 // Enqueues one fused pass of `n_items` work items with `threads` (256 or
-// 512) threads per workgroup.  Returns the launch status.
+// 512) threads per workgroup, for `n_images` same-shape images (see
+// PassArgs strides).  Returns the launch status.
 hipError_t launch_pass(Combo combo, const PassArgs &args, int n_items, int lds_bytes, int threads,
-                       hipStream_t stream);
+                       hipStream_t stream, int n_images = 1);
 
 // Adjoint (back-projection).  One gather step of one quadrant: rows of the
 // gradient of one frontier to those of the next frontier down (see
@@ -85,6 +89,8 @@ struct AdjJob {
 
 struct AdjArgs {
     AdjJob job[kInlineJobs];
+    // same-shape image batches (grid.z = image): bytes between images
+    int64_t src_stride, dst_stride;
 };
 
 // Sum of the quadrants' lane gradients into the image gradient (R x C):
@@ -95,6 +101,9 @@ struct CombineArgs {
     int32_t mirror[kInlineJobs];
     int32_t R, C;
     void *dst;
+    // same-shape image batches (grid.z = image): bytes between images of each
+    // source and of the destination
+    int64_t src_stride[kInlineJobs], dst_stride;
 };
 
 enum class Real { F32, F64 };
@@ -125,7 +134,8 @@ enum class PeakElem { I32, F32, F64 };
 hipError_t launch_peaks(PeakElem elem, const PeakArgs &args, int max_elems, hipStream_t stream);
 
 hipError_t launch_adjoint_step(Real real, const AdjArgs &args, int n_jobs, int max_w,
-                               hipStream_t stream);
-hipError_t launch_adjoint_combine(Real real, const CombineArgs &args, hipStream_t stream);
+                               hipStream_t stream, int n_images = 1);
+hipError_t launch_adjoint_combine(Real real, const CombineArgs &args, hipStream_t stream,
+                                  int n_images = 1);
 
 }  // namespace fht

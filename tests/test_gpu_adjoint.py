@@ -131,3 +131,41 @@ def test_uint8_adjoint_is_rejected():
     with pytest.raises(F.FhtError) as e:
         F.fht_adjoint(plan.handle, g.data_ptr(), g.data_ptr(), None, None)
     assert e.value.status == -2
+
+
+def test_adjoint_many_equals_single_images():
+    R, C, n = 61, 47, 5
+    plan = F.Plan(R, C, "f64", "T")
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    G = torch.randn(n, plan.out_elems, dtype=torch.float64, device="cuda", generator=gen)
+    many = plan.adjoint_many(G)
+    torch.cuda.synchronize()
+    for b in range(n):
+        assert torch.equal(many[b], plan.adjoint(G[b].contiguous())), b
+
+
+def test_gradcheck_f64_batch_2x13x11():
+    plan = F.Plan(13, 11, "f64", "S")
+    img = torch.randn(2, 13, 11, dtype=torch.float64, device="cuda", requires_grad=True)
+    assert torch.autograd.gradcheck(lambda x: F.HoughFunction.apply(x, plan), (img,),
+                                    eps=1e-6, atol=1e-7, rtol=1e-6)
+
+
+def test_autograd_batched_float32_384x257():
+    # config-4 shapes through the batched forward and adjoint
+    R, C, n = 384, 257, 3
+    rng = np.random.default_rng(2411_07351 + 4)
+    imgs = torch.from_numpy(rng.standard_normal((n, R, C)).astype(np.float32)).cuda()
+    imgs.requires_grad_(True)
+    quads = F.hough_autograd(imgs)
+    wts = [torch.from_numpy(rng.standard_normal(tuple(q.shape)).astype(np.float32)).cuda()
+           for q in quads]
+    loss = sum((q * w).sum() for q, w in zip(quads, wts))
+    loss.backward()
+    torch.cuda.synchronize()
+    for b in (0, n - 1):
+        Gs = {q: wts[q][b].double().cpu().numpy() for q in range(4)}
+        ref = O.adjoint4(Gs, 0, (R, C))
+        scale = O.adjoint4({q: np.abs(G) for q, G in Gs.items()}, 0, (R, C))
+        got = imgs.grad[b].double().cpu().numpy()
+        assert np.all(np.abs(got - ref) <= 1e-5 * scale)

@@ -207,3 +207,22 @@ def test_graph_replays_match_eager(F):
     ref = native.hough4_u8(imgs_np[3], 0)
     for q, g in enumerate(plans[3].split_out(outs[3])):
         assert (g.cpu().numpy() == ref[q]).all()
+
+
+@pytest.mark.parametrize("kind,shape,n", [("u8", (61, 47), 5), ("u8", (300, 200), 3),
+                                          ("f32", (129, 70), 4), ("u8", (1, 9), 2)])
+def test_forward_many_equals_single_images(F, kind, shape, n):
+    R, C = shape
+    rng = WL.rng_for(2, salt=40 + n)
+    if kind == "u8":
+        imgs = torch.from_numpy(np.stack([WL.uniform_u8(rng, R, C) for _ in range(n)])).cuda()
+    else:
+        imgs = torch.from_numpy(np.stack([WL.normal_f32(rng, R, C) for _ in range(n)])).cuda()
+    plan = F.Plan(R, C, kind, "S")
+    outs = plan.forward_many(imgs)
+    torch.cuda.synchronize()
+    for b in range(n):
+        solo = plan.new_out("cuda")
+        plan.forward(imgs[b], solo)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[b], solo), b
