@@ -344,11 +344,13 @@ __device__ __forceinline__ void store_rows(const TL *lds, const int4 *ent, int n
                 if (c < lim) {
                     const int s = s0 + c;
                     const int sm = s != 0 ? H - s : 0;
+                    // streaming stores: rows are written once and not re-read by this pass
                     if constexpr (PAIR_OUT) {
-                        rowp[s] = static_cast<TD>(pair_lo(v[k]));
-                        dst2[row + (unmirror ? sm : s)] = static_cast<TD>(pair_hi(v[k]));
+                        __builtin_nontemporal_store(static_cast<TD>(pair_lo(v[k])), rowp + s);
+                        __builtin_nontemporal_store(static_cast<TD>(pair_hi(v[k])),
+                                                    dst2 + row + (unmirror ? sm : s));
                     } else {
-                        rowp[unmirror ? sm : s] = static_cast<TD>(v[k]);
+                        __builtin_nontemporal_store(static_cast<TD>(v[k]), rowp + (unmirror ? sm : s));
                     }
                 }
             }

@@ -35,11 +35,14 @@ def _check_solo(reqs):
             assert torch.equal(a, b), f"request {r.rid} ({r.rows}x{r.cols} {r.kind}) quadrant {q}"
 
 
-def _serve(reqs, **kw):
+def _serve(reqs, warm_plans=False, **kw):
     torch.cuda.synchronize()
     srv = S.Server(S.GpuExecutor(streams=kw.pop("streams", 2)), kw.pop("budget", 4 << 30),
                    plan_threads=4, **kw)
     try:
+        if warm_plans:  # every plan ready at once: simultaneous arrivals form one batch
+            for r in reqs:
+                srv.plans.get(r.rows, r.cols, r.kind, r.split).result()
         srv.run(reqs)
     finally:
         srv.close()
@@ -76,10 +79,14 @@ def test_injected_enqueue_failure_fails_one_request_only():
 
 
 def test_injected_failure_of_a_batch_is_retried():
-    reqs = _requests(10, seed=13, qps=float("inf"), hi=300)
+    # the uint8 requests arrive at once with their plans ready, so
+    # the first enqueue (the one that fails) is a batch of several requests;
+    # its requests are retried one by one and all succeed
+    reqs = [r for r in _requests(14, seed=13, qps=float("inf"), hi=300) if r.kind == "u8"]
     F.fht_debug_fail_next(-4, 1)
     try:
-        _serve(reqs, max_batch_images=10)
+        srv = _serve(reqs, warm_plans=True, max_batch_images=len(reqs))
     finally:
         F.fht_debug_fail_next(0, 0)
+    assert srv.batch_sizes[0] == 1 and len(srv.batch_sizes) == len(reqs)  # the retries
     _check_solo(reqs)
