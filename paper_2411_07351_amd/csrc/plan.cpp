@@ -290,12 +290,21 @@ void build_pass(const Tree &tr, int lin, int lout, int T, int S, int K, int pad,
 void build_pass_fitted(const Tree &tr, int lin, int lout, int T, int target, int pad, int H,
                        Pass *out)
 {
-    // Windows are S plus a spread that does not depend on S: probe it with
-    // S = 16 (so that the probe itself fits), then pick the largest S.
-    const int Kmax = target / kChunk;
-    Pass probe;
-    build_pass(tr, lin, lout, T, 16, Kmax + 64, pad, H, &probe);
-    const int spread = probe.widest - 16;
+    // Windows are S plus a spread that does not depend on S (nor on K): take
+    // the widest window of every tile for S = 16, then pick the largest S.
+    std::vector<int> roots;
+    collect_frontier(tr, 0, lout, &roots);
+    int widest = 0;
+    for (int r : roots) {
+        const int w = tr.nodes[r].w;
+        const int tt = (T <= 0) ? w : T;
+        for (int ta = 0; ta < w; ta += tt) {
+            TileBuilder probe{tr, lin, 1, kChunk, {}};
+            probe.need(r, ta, std::min(w, ta + tt) - 1, 0, 16);
+            for (const Block &b : probe.blocks) widest = std::max(widest, b.width());
+        }
+    }
+    const int spread = widest - 16;
     const int S = std::min(H, std::max(16, target - spread));
     const int K = std::max(1, chunks_of(S + spread));
     build_pass(tr, lin, lout, T, S, K, pad, H, out);
