@@ -216,11 +216,14 @@ __device__ __forceinline__ void load_rows(TL *lds, const int4 *ent, int n, const
 // thread mapping follows the contiguous direction so that loads coalesce.
 //   rows: wavefront w takes lanes w + NW i, two lanes at a time
 //   cols: thread t takes lane t % XW and positions t / XW + k * (threads / XW)
-// Every thread issues all its loads (clamped in bounds) before the first LDS
-// write, so they are in flight together.  With PAIR every element is
+// Every thread issues a batch of loads (clamped in bounds) before their LDS
+// writes, so they are in flight together.  With PAIR every element is
 // (value at y) | (value at the mirrored position (H - y) mod H) << 16: the
 // positive- and negative-slope quadrants together.  ONE: the windows wrap
 // around at most once (load_end <= H).
+constexpr int ROWS_AT_ONCE = 4;  // lanes per wavefront whose loads are in flight together
+constexpr int COLS_AT_ONCE = 8;  // positions per thread whose loads are in flight together
+
 template <typename TL, typename TSrc, bool PAIR>
 __device__ __forceinline__ TL image_elem(TSrc a, TSrc b)
 {
@@ -245,7 +248,7 @@ __device__ __forceinline__ void load_image_impl(TL *lds, const int4 *ent, int nl
         const int4 mine = ent[xin ? x : nl - 1];
         const int wend = mine.z + 64 * K;
         const TSrc *colp = img + mine.y;
-        constexpr int U = 8;
+        constexpr int U = COLS_AT_ONCE;
         for (int p0 = threadIdx.x / XW; p0 < load_end; p0 += pstep * U) {
             TSrc a[U], b[U];
 #pragma unroll
@@ -265,14 +268,14 @@ __device__ __forceinline__ void load_image_impl(TL *lds, const int4 *ent, int nl
         }
     } else {
         const int4 mine = ent[lane < nl ? lane : nl - 1];
-        for (int x0 = wave; x0 < nl; x0 += 2 * NW) {
-            const int x1 = min(x0 + NW, nl - 1);
-            const bool two = x0 + NW < nl;
-            TSrc a[2 * K], b[2 * K];
+        // RW lanes per wavefront at a time (wavefront w takes lanes w + NW i)
+        constexpr int RW = ROWS_AT_ONCE;
+        for (int x0 = wave; x0 < nl; x0 += RW * NW) {
+            TSrc a[RW * K], b[RW * K];
 #pragma unroll
-            for (int q = 0; q < 2 * K; ++q) {
-                const int x = q < K ? x0 : x1;
-                const int k = q < K ? q : q - K;
+            for (int q = 0; q < RW * K; ++q) {
+                const int x = min(x0 + (q / K) * NW, nl - 1);
+                const int k = q % K;
                 const int y = wrap<ONE>(s0 + rl(mine.z, x) + 64 * k + lane, H);
                 const int ym = y != 0 ? H - y : 0;
                 const TSrc *rowp = img + static_cast<size_t>(rl(mine.y, x)) * ld;
@@ -280,10 +283,10 @@ __device__ __forceinline__ void load_image_impl(TL *lds, const int4 *ent, int nl
                 if constexpr (PAIR) b[q] = rowp[ym];
             }
 #pragma unroll
-            for (int q = 0; q < 2 * K; ++q) {
-                const int x = q < K ? x0 : x1;
-                const int k = q < K ? q : q - K;
-                if (q < K || two) lds[rl(mine.x, x) + 64 * k + lane] = image_elem<TL, TSrc, PAIR>(a[q], b[q]);
+            for (int q = 0; q < RW * K; ++q) {
+                const int xr = x0 + (q / K) * NW;
+                const int k = q % K;
+                if (xr < nl) lds[rl(mine.x, xr) + 64 * k + lane] = image_elem<TL, TSrc, PAIR>(a[q], b[q]);
             }
         }
     }
