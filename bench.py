@@ -218,7 +218,7 @@ def _differentiable(args, torch, F, WL):
             "per_image": {"value": round(px / (fb_ms * 1e-3) / 1e6, 1), "unit": "Mpixel/s",
                           "forward_ms": round(f_ms, 4), "adjoint_ms": round(b_ms, 4),
                           "forward_adjoint_ms": round(fb_ms, 4)},
-            "adjoint_launches": max(F.fht_plan_adjoint_tasks(plan.handle, v).shape[0]
+            "adjoint_launches": max(F.fht_plan_adjoint_num_passes(plan.handle, v)
                                     for v in (0, 1)) + 1}
 
 

@@ -228,7 +228,8 @@ fht_status fht_batch_upload(fht_batch batch, void *d_tables, size_t bytes, void 
  * (Alg. 2 patterns; A_q the lane view of quadrant q, sigma = +1 for V+/H+,
  * -1 for V-/H-), it computes
  *   gimg = sum_q view_q^T ( g_q[x][y] = sum_t gout_q[t][(y - sigma_q pat_t(x)) mod H] )
- * by running the merges of Alg. 1 backwards, one tree level per launch.
+ * by running the merges of Alg. 1 backwards, up to three tree levels per
+ * gather launch.
  *   d_gout device, fht_plan_out_elems elements in fht_forward's output layout
  *   d_gimg device, rows x cols, overwritten
  *   d_ws   device, fht_plan_adjoint_workspace_bytes bytes (NULL when 0)
@@ -243,6 +244,15 @@ size_t fht_plan_adjoint_workspace_bytes(fht_plan plan);
  * Errors: FHT_EINVAL, FHT_EDTYPE (uint8 plan). */
 fht_status fht_plan_adjoint_tasks(fht_plan plan, int32_t v, const int32_t **tasks,
                                   int32_t *levels, int32_t *lanes);
+/* The gather launches fht_adjoint runs for lane view v: those steps composed
+ * a few levels at a time.  fht_plan_adjoint_num_passes returns their number
+ * (-1 for a bad view or a uint8 plan); pass `pass` covers *levels steps:
+ *   g_out[x][s] = sum_{i in [offs[x], offs[x+1])} g_in[terms[2i]][(s - terms[2i+1]) mod H]
+ * with offs holding lanes + 1 entries and shifts already reduced mod H.
+ * Pointers are valid while the plan lives.  Errors: FHT_EINVAL. */
+int32_t fht_plan_adjoint_num_passes(fht_plan plan, int32_t v);
+fht_status fht_plan_adjoint_pass(fht_plan plan, int32_t v, int32_t pass, int32_t *levels,
+                                 const int32_t **offs, const int32_t **terms, int32_t *n_terms);
 fht_status fht_adjoint(fht_plan plan, const void *d_gout, void *d_gimg, void *d_ws, void *stream);
 /* fht_adjoint for n same-shape images: output gradient b at d_gouts +
  * b * gout_stride, image gradient b at d_gimgs + b * gimg_stride (bytes);

@@ -38,6 +38,7 @@ __all__ = [
     "HoughFunction", "hough_autograd", "fht_peaks_workspace_bytes", "fht_peaks", "PEAK_DTYPE",
     "fht_plan_work", "fht_plan_launch_kernel", "fht_plan_workspace_bytes_many",
     "fht_forward_many", "fht_plan_adjoint_workspace_bytes_many", "fht_adjoint_many",
+    "fht_plan_adjoint_num_passes", "fht_plan_adjoint_pass",
 ]
 
 FHT_U8, FHT_F32, FHT_F64 = 0, 1, 2
@@ -58,7 +59,7 @@ EXPORTED = (
     "fht_plan_adjoint_workspace_bytes", "fht_plan_adjoint_tasks", "fht_adjoint",
     "fht_peaks_workspace_bytes", "fht_peaks", "fht_plan_work", "fht_plan_launch_kernel",
     "fht_plan_workspace_bytes_many", "fht_forward_many", "fht_plan_adjoint_workspace_bytes_many",
-    "fht_adjoint_many",
+    "fht_adjoint_many", "fht_plan_adjoint_num_passes", "fht_plan_adjoint_pass",
 )
 
 # struct fht_peak
@@ -120,6 +121,8 @@ _sig("fht_debug_fail_next", None, _i32, _i32)
 _sig("fht_plan_adjoint_workspace_bytes", _sz, _vp)
 _sig("fht_plan_adjoint_tasks", _i32, _vp, _i32, _ppi32, _pi32, _pi32)
 _sig("fht_adjoint", _i32, _vp, _vp, _vp, _vp, _vp)
+_sig("fht_plan_adjoint_num_passes", _i32, _vp, _i32)
+_sig("fht_plan_adjoint_pass", _i32, _vp, _i32, _i32, _pi32, _ppi32, _ppi32, _pi32)
 _sig("fht_peaks_workspace_bytes", _sz, _i32)
 _sig("fht_peaks", _i32, _vp, _vp, _i32, _i32, ctypes.c_double, _i32, _vp, _vp, _vp, _vp)
 _sig("fht_plan_num_passes", _i32, _vp, _i32)
@@ -291,6 +294,24 @@ def fht_plan_adjoint_tasks(plan: int, view: int) -> np.ndarray:
     if n == 0:
         return np.zeros((levels.value, lanes.value, 4), dtype=np.int32)
     return np.ctypeslib.as_array(tasks, shape=(n,)).reshape(levels.value, lanes.value, 4).copy()
+
+
+def fht_plan_adjoint_num_passes(plan: int, view: int) -> int:
+    return _lib.fht_plan_adjoint_num_passes(plan, view)
+
+
+def fht_plan_adjoint_pass(plan: int, view: int, pass_idx: int) -> dict:
+    """Copy of one fused adjoint gather pass: levels, offs (lanes + 1), terms (n, 2)."""
+    levels, nterms = _i32(), _i32()
+    offs, terms = _pi32(), _pi32()
+    _check(_lib.fht_plan_adjoint_pass(plan, view, pass_idx, ctypes.byref(levels), ctypes.byref(offs),
+                                      ctypes.byref(terms), ctypes.byref(nterms)),
+           "fht_plan_adjoint_pass")
+    lanes = fht_plan_adjoint_tasks(plan, view).shape[1]
+    o = np.ctypeslib.as_array(offs, shape=(lanes + 1,)).copy()
+    t = (np.ctypeslib.as_array(terms, shape=(2 * nterms.value,)).reshape(-1, 2).copy()
+         if nterms.value else np.zeros((0, 2), dtype=np.int32))
+    return {"levels": levels.value, "offs": o, "terms": t}
 
 
 def fht_adjoint(plan: int, d_gout: int, d_gimg: int, d_ws: int | None, stream: int | None) -> None:

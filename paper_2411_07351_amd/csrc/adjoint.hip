@@ -4,12 +4,14 @@
 // The transform is linear: out[t][s] = sum_x A[x][(s + pat_t(x)) mod H] for
 // every quadrant view A (Sec. 3; negative slopes run in a mirrored position
 // frame).  Its adjoint sends an output gradient G back along the same
-// patterns.  It is computed by running the merges of Alg. 1 backwards, one
-// tree level per launch: each lane row of a child gathers the contiguous
-// range of parent rows that read it, the right child's rows rotated back by
-// the shift they were given.  A final launch adds the quadrants' lane
-// gradients into the image gradient, transposing the column-lane quadrants
-// through LDS.  Memory-bound gathers: no MFMA.
+// patterns.  It is computed by running the merges of Alg. 1 backwards: each
+// lane row of a child gathers the contiguous range of parent rows that read
+// it, the right child's rows rotated back by the shift they were given.
+// Several levels go in one launch as a gather over the composed terms (about
+// 2^levels rows per output row, adjacent rows sharing them in L2).  A final
+// launch adds the quadrants' lane gradients into the image gradient,
+// transposing the column-lane quadrants through LDS.  Memory-bound gathers:
+// no MFMA.
 #include "kernels.hpp"
 
 namespace fht {
@@ -27,36 +29,51 @@ __global__ void __launch_bounds__(256) adj_step_kernel(AdjArgs args)
     const int x = blockIdx.x * kRowsPerBlock + wave;
     if (x >= job.W) return;
     const int H = job.H;
-    const int4 task = job.tasks[x];
-    const int p0 = __builtin_amdgcn_readfirstlane(task.x);
-    const int n = __builtin_amdgcn_readfirstlane(task.y);
-    const int r0 = __builtin_amdgcn_readfirstlane(task.z);
-    const bool right = __builtin_amdgcn_readfirstlane(task.w) != 0;
     const int64_t b = blockIdx.z;  // image of a same-shape batch
     const T *src = reinterpret_cast<const T *>(static_cast<const char *>(job.src) + b * args.src_stride);
     T *dst = reinterpret_cast<T *>(static_cast<char *>(job.dst) + b * args.dst_stride) +
              static_cast<size_t>(x) * H;
     const bool mirror = job.mirror_in != 0;
+    const int t0 = job.offs[x], t1 = job.offs[x + 1];
+    // The row's terms reach the wavefront 64 at a time through one vector
+    // load and are broadcast with readlane, so no load waits per term.
+    const int m0 = min(64, t1 - t0);
+    const int2 first = lane < m0 ? job.terms[t0 + lane] : make_int2(0, 0);
+    // four terms times four 64-position chunks of loads in flight together
     for (int s0 = 0; s0 < H; s0 += 256) {
         T acc[4] = {T(0), T(0), T(0), T(0)};
-        for (int j = 0; j < n; ++j) {
-            const int shift = right ? (r0 + j) % H : 0;
-            const T *row = src + static_cast<size_t>(p0 + j) * H;
+        for (int tb = t0; tb < t1; tb += 64) {
+            const int m = min(64, t1 - tb);
+            const int2 mine = tb == t0 ? first : (lane < m ? job.terms[tb + lane] : make_int2(0, 0));
+            for (int j0 = 0; j0 < m; j0 += 4) {
+                T v[4][4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int s = s0 + 64 * u + lane;
-                if (s < H) {
-                    int y = s - shift;
-                    if (y < 0) y += H;
-                    if (mirror && y != 0) y = H - y;
-                    acc[u] += row[y];
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int j = min(j0 + jj, m - 1);
+                    const int rowi = __builtin_amdgcn_readlane(mine.x, j);
+                    const int sh = __builtin_amdgcn_readlane(mine.y, j);
+                    const T *row = src + static_cast<size_t>(rowi) * H;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int s = min(s0 + 64 * u + lane, H - 1);
+                        int y = s - sh;
+                        if (y < 0) y += H;
+                        if (mirror && y != 0) y = H - y;
+                        v[jj][u] = row[y];
+                    }
                 }
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+                    if (j0 + jj < m) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) acc[u] += v[jj][u];
+                    }
             }
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int s = s0 + 64 * u + lane;
-            if (s < H) dst[s] = acc[u];
+            if (s < H) __builtin_nontemporal_store(acc[u], dst + s);
         }
     }
 }

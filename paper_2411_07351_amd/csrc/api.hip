@@ -58,6 +58,9 @@ hipError_t upload(const std::vector<T> &host, T **dev)
 // uint8 images keep 16-bit sums while nodes are at most this wide.
 constexpr int kNarrowWidth = 257;
 
+// Tree levels per adjoint gather launch.
+constexpr int kAdjointFuse = 3;
+
 // Element types of pass p of an axis plan (see fht::Combo); `pair` selects
 // the quadrant-pair form.
 Combo pass_combo(fht_dtype dt, const fht::AxisPlan &ax, size_t p, bool pair)
@@ -200,13 +203,16 @@ struct ViewProgs {
 struct DevTables {
     int device = -1;
     const DevProgs *views[2] = {nullptr, nullptr};
-    std::vector<int32_t *> items;          // per launch
-    int32_t *adj[2] = {nullptr, nullptr};  // adjoint tasks per lane view
+    std::vector<int32_t *> items;               // per launch
+    int32_t *adj_offs[2] = {nullptr, nullptr};   // fused adjoint passes per lane view
+    int32_t *adj_terms[2] = {nullptr, nullptr};
 };
 
 void free_tables(DevTables &t)
 {
-    for (int32_t *p : t.adj)
+    for (int32_t *p : t.adj_offs)
+        if (p) (void)hipFree(p);
+    for (int32_t *p : t.adj_terms)
         if (p) (void)hipFree(p);
     for (int32_t *p : t.items)
         if (p) (void)hipFree(p);
@@ -325,6 +331,8 @@ struct fht_plan_s {
     size_t ws_bytes = 0;
     std::vector<Launch> launches;    // in level order
     fht::AdjointAxis adj[2];         // adjoint steps per lane view (float plans)
+    std::vector<fht::AdjointPass> adjp[2];          // the steps fused into gather passes
+    std::vector<size_t> adjp_offs[2], adjp_terms[2];  // where pass p starts in the tables
     size_t adj_ws_off[4][2] = {};
     size_t adj_ws_bytes = 0;
     std::mutex mu;
@@ -364,7 +372,15 @@ struct fht_plan_s {
             e = upload(launches[l].items, &ptr);
             t.items.push_back(ptr);
         }
-        for (int v = 0; e == hipSuccess && v < 2; ++v) e = upload(adj[v].tasks, &t.adj[v]);
+        for (int v = 0; e == hipSuccess && v < 2; ++v) {
+            std::vector<int32_t> offs, terms;
+            for (const fht::AdjointPass &ap : adjp[v]) {
+                offs.insert(offs.end(), ap.offs.begin(), ap.offs.end());
+                terms.insert(terms.end(), ap.terms.begin(), ap.terms.end());
+            }
+            e = upload(offs, &t.adj_offs[v]);
+            if (e == hipSuccess) e = upload(terms, &t.adj_terms[v]);
+        }
         if (e != hipSuccess) {
             free_tables(t);
             return hip_status(e);
@@ -741,15 +757,24 @@ fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, fht_dtype 
         p->ws_bytes = ws;
         // Adjoint steps and their ping-pong buffers (float plans).
         if (dtype != FHT_U8) {
-            for (int v = 0; v < 2; ++v)
-                if (quadrant_mask & (3u << (2 * v)))
-                    p->adj[v] = fht::plan_adjoint_axis(v == 0 ? rows : cols, static_cast<int>(split));
+            for (int v = 0; v < 2; ++v) {
+                if (!(quadrant_mask & (3u << (2 * v)))) continue;
+                p->adj[v] = fht::plan_adjoint_axis(v == 0 ? rows : cols, static_cast<int>(split));
+                p->adjp[v] = fht::fuse_adjoint(p->adj[v], v == 0 ? cols : rows, kAdjointFuse);
+                size_t ob = 0, tb = 0;
+                for (const fht::AdjointPass &ap : p->adjp[v]) {
+                    p->adjp_offs[v].push_back(ob);
+                    p->adjp_terms[v].push_back(tb);
+                    ob += ap.offs.size();
+                    tb += ap.terms.size() / 2;
+                }
+            }
             size_t aws = 0;
             for (int q = 0; q < 4; ++q) {
                 if (!(quadrant_mask & (1u << q))) continue;
-                const fht::AdjointAxis &ax = p->adj[q >> 1];
+                const int npass = static_cast<int>(p->adjp[q >> 1].size());
                 const size_t wh = static_cast<size_t>(rows) * cols;
-                for (int b = 0; b < std::min(ax.levels, 2); ++b) {
+                for (int b = 0; b < std::min(npass, 2); ++b) {
                     p->adj_ws_off[q][b] = aws;
                     aws += align_up(wh * eb, 256);
                 }
@@ -1047,6 +1072,25 @@ fht_status fht_plan_work(fht_plan plan, int64_t *adds_tree, int64_t *adds_execut
 
 size_t fht_plan_adjoint_workspace_bytes(fht_plan plan) { return plan ? plan->adj_ws_bytes : 0; }
 
+int32_t fht_plan_adjoint_num_passes(fht_plan plan, int32_t v)
+{
+    if (!plan || v < 0 || v > 1 || !(plan->qmask & (3u << (2 * v))) || plan->dtype == FHT_U8)
+        return -1;
+    return static_cast<int32_t>(plan->adjp[v].size());
+}
+
+fht_status fht_plan_adjoint_pass(fht_plan plan, int32_t v, int32_t pass, int32_t *levels,
+                                 const int32_t **offs, const int32_t **terms, int32_t *n_terms)
+{
+    if (fht_plan_adjoint_num_passes(plan, v) <= pass || pass < 0) return FHT_EINVAL;
+    const fht::AdjointPass &ap = plan->adjp[v][pass];
+    if (levels) *levels = ap.levels;
+    if (offs) *offs = ap.offs.data();
+    if (terms) *terms = ap.terms.data();
+    if (n_terms) *n_terms = static_cast<int32_t>(ap.terms.size() / 2);
+    return FHT_OK;
+}
+
 fht_status fht_plan_adjoint_tasks(fht_plan plan, int32_t v, const int32_t **tasks,
                                   int32_t *levels, int32_t *lanes)
 {
@@ -1084,10 +1128,11 @@ fht_status fht_adjoint_many(fht_plan plan, int32_t n, const void *d_gouts, int64
     hipStream_t hs = static_cast<hipStream_t>(stream);
     char *ws = static_cast<char *>(d_ws);
     const char *gout = static_cast<const char *>(d_gouts);
-    int max_levels = 0;
+    int max_passes = 0;
     for (int q = 0; q < 4; ++q)
-        if (plan->qmask & (1u << q)) max_levels = std::max(max_levels, plan->adj[q >> 1].levels);
-    for (int k = 0; k < max_levels; ++k) {
+        if (plan->qmask & (1u << q))
+            max_passes = std::max(max_passes, static_cast<int>(plan->adjp[q >> 1].size()));
+    for (int k = 0; k < max_passes; ++k) {
         fht::AdjArgs a;
         std::memset(&a, 0, sizeof(a));
         a.src_stride = k == 0 ? gout_stride : ws_stride;
@@ -1095,14 +1140,15 @@ fht_status fht_adjoint_many(fht_plan plan, int32_t n, const void *d_gouts, int64
         int nj = 0, max_w = 0;
         for (int q = 0; q < 4; ++q) {
             if (!(plan->qmask & (1u << q))) continue;
-            const fht::AdjointAxis &ax = plan->adj[q >> 1];
-            if (ax.levels <= k) continue;
+            const int v = q >> 1;
+            const fht::AdjointAxis &ax = plan->adj[v];
+            if (static_cast<int>(plan->adjp[v].size()) <= k) continue;
             fht::AdjJob &j = a.job[nj++];
             j.src = k == 0 ? static_cast<const void *>(gout + plan->out_off[q] * eb)
                            : static_cast<const void *>(ws + plan->adj_ws_off[q][(k - 1) & 1]);
             j.dst = ws + plan->adj_ws_off[q][k & 1];
-            j.tasks = reinterpret_cast<const int4 *>(t->adj[q >> 1] +
-                                                     static_cast<size_t>(k) * ax.W * 4);
+            j.offs = t->adj_offs[v] + plan->adjp_offs[v][k];
+            j.terms = reinterpret_cast<const int2 *>(t->adj_terms[v]) + plan->adjp_terms[v][k];
             j.W = ax.W;
             j.H = (q >> 1) ? plan->R : plan->C;
             j.mirror_in = (k == 0 && (q & 1)) ? 1 : 0;
@@ -1119,7 +1165,7 @@ fht_status fht_adjoint_many(fht_plan plan, int32_t n, const void *d_gouts, int64
     c.dst_stride = gimg_stride;
     for (int q = 0; q < 4; ++q) {
         if (!(plan->qmask & (1u << q))) continue;
-        const int L = plan->adj[q >> 1].levels;
+        const int L = static_cast<int>(plan->adjp[q >> 1].size());
         // after the steps a negative-slope quadrant is in the mirrored frame
         c.src[q] = L > 0 ? static_cast<const void *>(ws + plan->adj_ws_off[q][(L - 1) & 1])
                          : static_cast<const void *>(gout + plan->out_off[q] * eb);

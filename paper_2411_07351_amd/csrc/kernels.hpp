@@ -75,15 +75,16 @@ enum class Combo {
 hipError_t launch_pass(Combo combo, const PassArgs &args, int n_items, int lds_bytes, int threads,
                        hipStream_t stream, int n_images = 1);
 
-// Adjoint (back-projection).  One gather step of one quadrant: rows of the
-// gradient of one frontier to those of the next frontier down (see
-// fht::AdjointAxis for the task format).
+// Adjoint (back-projection).  One fused gather pass of one quadrant: rows of
+// the gradient of one frontier to those of a frontier several levels down
+// (see fht::AdjointPass for the term format).
 struct AdjJob {
-    const void *src;     // [W][H] gradient rows in (the output gradient at step 0)
-    void *dst;           // [W][H] gradient rows out
-    const int4 *tasks;   // W tasks {p0, n, r0, right}
+    const void *src;       // [W][H] gradient rows in (the output gradient in pass 0)
+    void *dst;             // [W][H] gradient rows out
+    const int32_t *offs;   // W + 1 term offsets
+    const int2 *terms;     // {source row, shift mod H}
     int32_t W, H;
-    int32_t mirror_in;   // read src at mirrored positions (step 0 of V-/H-)
+    int32_t mirror_in;     // read src at mirrored positions (pass 0 of V-/H-)
     int32_t pad;
 };
 

@@ -447,4 +447,39 @@ AdjointAxis plan_adjoint_axis(int W, int split)
     return ax;
 }
 
+std::vector<AdjointPass> fuse_adjoint(const AdjointAxis &ax, int H, int max_levels)
+{
+    std::vector<AdjointPass> passes;
+    const int W = ax.W;
+    max_levels = std::max(1, max_levels);
+    for (int k0 = 0; k0 < ax.levels; k0 += max_levels) {
+        const int k1 = std::min(ax.levels, k0 + max_levels);
+        AdjointPass p;
+        p.levels = k1 - k0;
+        p.offs.reserve(static_cast<size_t>(W) + 1);
+        std::vector<int64_t> cur, nxt;  // (row, shift) pairs, shifts mod H
+        for (int x = 0; x < W; ++x) {
+            p.offs.push_back(static_cast<int32_t>(p.terms.size() / 2));
+            cur.assign({x, 0});
+            // walk up from the last step of the pass to its first
+            for (int k = k1 - 1; k >= k0; --k) {
+                const int32_t *task = ax.tasks.data() + static_cast<size_t>(k) * W * 4;
+                nxt.clear();
+                for (size_t i = 0; i < cur.size(); i += 2) {
+                    const int32_t *e = task + 4 * cur[i];
+                    for (int j = 0; j < e[1]; ++j) {
+                        nxt.push_back(e[0] + j);
+                        nxt.push_back((cur[i + 1] + (e[3] ? e[2] + j : 0)) % H);
+                    }
+                }
+                cur.swap(nxt);
+            }
+            for (int64_t v : cur) p.terms.push_back(static_cast<int32_t>(v));
+        }
+        p.offs.push_back(static_cast<int32_t>(p.terms.size() / 2));
+        passes.push_back(std::move(p));
+    }
+    return passes;
+}
+
 }  // namespace fht

@@ -113,4 +113,19 @@ struct AdjointAxis {
 
 AdjointAxis plan_adjoint_axis(int W, int split);
 
+// The adjoint's steps fused into gathers of up to `max_levels` levels each
+// (top down): pass p maps the gradients of one frontier to those `levels`
+// levels further down, in one launch,
+//   g_out[x][s] = sum_{i in [offs[x], offs[x+1])} g_in[row_i][(s - shift_i) mod H],
+// with terms[2 i] = row_i, terms[2 i + 1] = shift_i mod H: the composition
+// of the single steps (shifts add along each path; the preimages partition
+// the rows, so no term repeats).
+struct AdjointPass {
+    int levels = 0;
+    std::vector<int32_t> offs;   // W + 1
+    std::vector<int32_t> terms;  // 2 per term
+};
+
+std::vector<AdjointPass> fuse_adjoint(const AdjointAxis &ax, int H, int max_levels);
+
 }  // namespace fht

@@ -78,3 +78,43 @@ def test_uint8_plans_have_no_adjoint():
         F.fht_plan_adjoint_tasks(plan.handle, 0)
     assert e.value.status == -2
     assert F.fht_plan_adjoint_workspace_bytes(plan.handle) == 0
+
+
+def interpret_fused(plan, Gs, R, C):
+    """The gather launches fht_adjoint runs (fused passes), executed in NumPy."""
+    g = np.zeros((R, C))
+    for q, G in Gs.items():
+        v = q >> 1
+        W, H = G.shape
+        cur = _mirror(G) if q & 1 else G.astype(np.float64)
+        y = np.arange(H)
+        levels = 0
+        for p in range(F.fht_plan_adjoint_num_passes(plan.handle, v)):
+            ps = F.fht_plan_adjoint_pass(plan.handle, v, p)
+            offs, terms = ps["offs"], ps["terms"]
+            levels += ps["levels"]
+            assert offs.shape == (W + 1,) and offs[0] == 0 and offs[-1] == len(terms)
+            assert (np.diff(offs) >= 1).all()
+            assert ((terms[:, 0] >= 0) & (terms[:, 0] < W)).all()
+            assert ((terms[:, 1] >= 0) & (terms[:, 1] < H)).all()
+            nxt = np.zeros((W, H))
+            for x in range(W):
+                for row, sh in terms[offs[x]:offs[x + 1]]:
+                    nxt[x] += cur[row][(y - sh) % H]
+            cur = nxt
+        assert levels == F.fht_plan_adjoint_tasks(plan.handle, v).shape[0]
+        gA = _mirror(cur) if q & 1 else cur
+        g += gA if q < 2 else gA.T
+    return g
+
+
+@pytest.mark.parametrize("split", ["S", "T"])
+@pytest.mark.parametrize("shape", [(1, 1), (1, 7), (7, 1), (13, 11), (16, 3), (17, 5), (33, 7),
+                                   (100, 37), (129, 5), (61, 47)])
+def test_fused_adjoint_passes_equal_oracle(split, shape):
+    R, C = shape
+    plan = F.Plan(R, C, "f64", split)
+    rng = np.random.default_rng(R * 1000 + C + 7)
+    Gs = {q: rng.integers(-7, 8, size=plan.shapes[q]).astype(np.float64) for q in range(4)}
+    ref = O.adjoint4(Gs, 0 if split == "S" else 1, (R, C))
+    np.testing.assert_array_equal(interpret_fused(plan, Gs, R, C), ref)
