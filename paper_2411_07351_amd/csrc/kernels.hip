@@ -303,9 +303,10 @@ __device__ __forceinline__ void load_image(TL *lds, const int4 *ent, int nl, int
         load_image_impl<K, NW, TSrc, TL, PAIR, false>(lds, ent, nl, load_end, img, job, s0, wave, lane);
 }
 
-// Stores {src, row, limit, K}: dst[row][s0 + c] = lds[src + c] for c < limit
-// and s0 + c < H; the final output of a negative-slope quadrant is written
-// back in un-mirrored position order.
+// Stores {src, row, limit, src1}: dst[row][s0 + c] = lds[src + c] for
+// c < limit and s0 + c < H, plus lds[src1 + c] when MERGE (the pass root's
+// last merge, done on the way out); the final output of a negative-slope
+// quadrant is written back in un-mirrored position order.
 // The two sums of a pair element: 16-bit halves of 32 bits, or the
 // components of a 32-bit pair.
 template <typename TL>
@@ -325,7 +326,7 @@ __device__ __forceinline__ uint32_t pair_hi(TL v)
 // With PAIR_OUT each pair is split into two int32 rows: the positive-slope
 // sum to dst, the negative-slope sum (mirrored frame) to dst2, stored at the
 // un-mirrored position when `unmirror` (the final output).
-template <int K, int NW, typename TL, typename TD, bool PAIR_OUT>
+template <int K, int NW, typename TL, typename TD, bool PAIR_OUT, bool MERGE>
 __device__ __forceinline__ void store_rows(const TL *lds, const int4 *ent, int n, TD *dst,
                                            TD *dst2, int H, int s0, bool unmirror, int wave,
                                            int lane)
@@ -341,6 +342,14 @@ __device__ __forceinline__ void store_rows(const TL *lds, const int4 *ent, int n
             TL v[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) v[k] = srcp[64 * k];
+            if constexpr (MERGE) {
+                const TL *src1 = lds + rl(mine.w, j) + lane;
+                TL w[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) w[k] = src1[64 * k];
+#pragma unroll
+                for (int k = 0; k < K; ++k) v[k] = static_cast<TL>(v[k] + w[k]);
+            }
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const int c = 64 * k + lane;
@@ -403,8 +412,14 @@ __device__ __forceinline__ void run_item(TL *lds, cptr<int32_t> hdr, const int4 
 
     constexpr bool PAIR_OUT = PAIR && sizeof(TD) == 4 && std::is_signed<TD>::value;
     const bool unmirror = (job.flags & JF_FINAL) && (PAIR_OUT || (job.flags & JF_MIRROR));
-    store_rows<K, NW, TL, TD, PAIR_OUT>(lds, step_ent, nstore, reinterpret_cast<TD *>(dst),
-                                        reinterpret_cast<TD *>(dst2), H, s0, unmirror, wave, lane);
+    if (hdr[27])  // the stores add the root's last merge
+        store_rows<K, NW, TL, TD, PAIR_OUT, true>(lds, step_ent, nstore, reinterpret_cast<TD *>(dst),
+                                                  reinterpret_cast<TD *>(dst2), H, s0, unmirror,
+                                                  wave, lane);
+    else
+        store_rows<K, NW, TL, TD, PAIR_OUT, false>(lds, step_ent, nstore, reinterpret_cast<TD *>(dst),
+                                                   reinterpret_cast<TD *>(dst2), H, s0, unmirror,
+                                                   wave, lane);
 }
 
 // TSrc / TL / TD: element types read, kept in LDS and written (see Combo).

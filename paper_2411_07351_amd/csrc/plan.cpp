@@ -8,13 +8,17 @@
 // emits a straight-line program of row entries (k = 64-position chunks):
 //   load   lds[d + c] = src[row][(s0 + off + c) mod H]             c < 64 k
 //   merge  lds[d + c] = lds[a + c] + lds[b + c]                      c < 64 k
-//   store  dst[row][s0 + c] = lds[d + c]                 c < min(64 k, lim), s0 + c < H
+//   store  dst[row][s0 + c] = lds[d + c] (+ lds[b + c])  c < min(64 k, lim), s0 + c < H
 // A merge is the vector operation of Alg. 1: row t of a node is row t0 of its
 // left child plus row t1 of its right child rotated by r = t - t1, with
 // t_P = [t (w_P - 1)/(w - 1)] rounded half to even.  Rotation is folded into
 // the LDS address of the right operand: every node keeps a window of
 // positions [lo, hi) relative to the tile start, and the right child's window
 // is widened by the range of r over the rows the tile needs.
+//
+// The last merge of a pass root is done by its stores: each store entry adds
+// the two child rows on the way out, so the root's rows never pass through
+// LDS (one LDS write and one read less per output element).
 //
 // Rows are stored with a stride rounded up to whole chunks and every entry
 // runs whole chunks: the positions past a window are computed but never
@@ -96,10 +100,11 @@ struct Block {
     int off = -1;     // LDS element offset
     int overrun = 0;  // positions a merge reads past the end of the last row
     int row_stride = 0;
+    bool virt = false;  // computed by the stores, never held in LDS
     int width() const { return hi - lo; }
     int rows() const { return uhi - ulo + 1; }
     int stride() const { return row_stride; }
-    int size() const { return rows() * stride() + overrun; }
+    int size() const { return virt ? 0 : rows() * stride() + overrun; }
 };
 
 struct TileBuilder {
@@ -187,7 +192,9 @@ void collect_frontier(const Tree &tr, int ni, int level, std::vector<int> *out)
 //   load   {lds row start, source row, position offset, K}; in the first
 //          pass there is one per lane, in lane order
 //   merge  {lds dst, lds src0, lds src1, K}
-//   store  {lds row start, destination row, position limit, K}
+//   store  {lds row start, destination row, position limit, lds src1 or -1}:
+//          with src1 >= 0 (every store of a program with merges) the stored
+//          value is lds[start + c] + lds[src1 + c], the root's last merge
 void emit_tile(const Tree &tr, int root, int ta, int tb, int lin, int S, int K, int pad,
                Pass *pass)
 {
@@ -196,6 +203,7 @@ void emit_tile(const Tree &tr, int root, int ta, int tb, int lin, int S, int K, 
     std::vector<Block> &bl = tb_.blocks;
     const int nsteps = std::max(0, tr.nodes[root].height - lin);
     bl[rb].last = nsteps + 1;
+    bl[rb].virt = nsteps > 0;  // the stores compute it
     const int lds = place(bl);
 
     int32_t hdr[kHdrInts] = {0};
@@ -216,20 +224,25 @@ void emit_tile(const Tree &tr, int root, int ta, int tb, int lin, int S, int K, 
             load_end = std::max(load_end, b.lo + K * kChunk);
         }
     }
-    for (int k = 1; k <= nsteps; ++k) {
+    // LDS offsets of the two operands of row u of computed block b
+    auto operands = [&](const Block &b, int u) {
+        const Node &n = tr.nodes[b.node];
+        const Block &L = bl[b.lb], &R = bl[b.rb];
+        const int w = n.w, w0 = n.w0, w1 = w - w0;
+        const int t0 = static_cast<int>(round_half_even(int64_t(u) * (w0 - 1), w - 1));
+        const int t1 = static_cast<int>(round_half_even(int64_t(u) * (w1 - 1), w - 1));
+        const int r = u - t1;
+        return std::make_pair(L.off + (t0 - L.ulo) * L.stride() + (b.lo - L.lo),
+                              R.off + (t1 - R.ulo) * R.stride() + (b.lo + r - R.lo));
+    };
+    const int lds_steps = std::max(0, nsteps - 1);  // the last one is the stores'
+    for (int k = 1; k <= lds_steps; ++k) {
         int cnt = 0;
         for (const Block &b : bl) {
             if (b.step != k) continue;
-            const Node &n = tr.nodes[b.node];
-            const Block &L = bl[b.lb], &R = bl[b.rb];
-            const int w = n.w, w0 = n.w0, w1 = w - w0;
             for (int u = b.ulo; u <= b.uhi; ++u, ++cnt) {
-                const int t0 = static_cast<int>(round_half_even(int64_t(u) * (w0 - 1), w - 1));
-                const int t1 = static_cast<int>(round_half_even(int64_t(u) * (w1 - 1), w - 1));
-                const int r = u - t1;
-                push(b.off + (u - b.ulo) * b.stride(),
-                     L.off + (t0 - L.ulo) * L.stride() + (b.lo - L.lo),
-                     R.off + (t1 - R.ulo) * R.stride() + (b.lo + r - R.lo), K);
+                const auto ab = operands(b, u);
+                push(b.off + (u - b.ulo) * b.stride(), ab.first, ab.second, K);
             }
         }
         hdr[8 + k - 1] = cnt;
@@ -238,13 +251,19 @@ void emit_tile(const Tree &tr, int root, int ta, int tb, int lin, int S, int K, 
     {
         const Block &b = bl[rb];
         const Node &n = tr.nodes[b.node];
-        for (int u = b.ulo; u <= b.uhi; ++u, ++nstore)
-            push(b.off + (u - b.ulo) * b.stride(), n.a + u, S, K);
+        for (int u = b.ulo; u <= b.uhi; ++u, ++nstore) {
+            if (b.virt) {
+                const auto ab = operands(b, u);
+                push(ab.first, n.a + u, S, ab.second);
+            } else {
+                push(b.off + (u - b.ulo) * b.stride(), n.a + u, S, -1);
+            }
+        }
     }
     hdr[0] = first;
     hdr[1] = nload;
     hdr[2] = nstore;
-    hdr[3] = nsteps;
+    hdr[3] = lds_steps;
     hdr[4] = lds;
     hdr[5] = static_cast<int>(pass->ops.size() / 4) - first;
     hdr[6] = lin;
@@ -252,6 +271,7 @@ void emit_tile(const Tree &tr, int root, int ta, int tb, int lin, int S, int K, 
     hdr[kHdrLoadEnd] = load_end;
     hdr[kHdrSTile] = S;
     hdr[kHdrChunks] = K;
+    hdr[kHdrStoreMerge] = bl[rb].virt ? 1 : 0;
     pass->hdrs.insert(pass->hdrs.end(), hdr, hdr + kHdrInts);
     pass->max_lds_elems = std::max(pass->max_lds_elems, lds);
     pass->widest = std::max(pass->widest, widest);

@@ -5,8 +5,9 @@ them and checks the invariants the kernel relies on:
 
 * entries cover whole 64-position chunks: load ``lds[d + c] = src[row][(s0 +
   off + c) mod H]``, merge ``lds[d + c] = lds[a + c] + lds[b + c]`` for
-  ``c < 64 k``; store ``dst[row][s0 + c] = lds[d + c]`` for ``c < min(64 k,
-  limit)`` and ``s0 + c < H``;
+  ``c < 64 k``; store ``dst[row][s0 + c] = lds[d + c]`` (``+ lds[b + c]``
+  when the header says the stores add the root's last merge) for
+  ``c < min(64 k, limit)`` and ``s0 + c < H``;
 * every LDS access stays inside the program's footprint;
 * no merge step reads a range another entry of the same step writes;
 * every stored value was computed from loaded data only (positions a window
@@ -40,6 +41,10 @@ def run_plan_tables(plan_handle, img, q, check=True):
         for prog, _, s0, _ in tb["items"]:
             hdr = tb["hdrs"][prog]
             first, nload, nstore, nsteps, lds_n, nops = (int(x) for x in hdr[:6])
+            K, store_merge = int(hdr[26]), bool(hdr[27])
+            if check:
+                # programs with merges fold the last one into the stores
+                assert store_merge == (int(hdr[7]) > int(hdr[6]))
             assert nops == nload + nstore + sum(int(c) for c in hdr[8:8 + nsteps])
             assert int(hdr[25]) == tb["s_tile"]
             ops = tb["ops"][first:first + nops]
@@ -79,12 +84,19 @@ def run_plan_tables(plan_handle, img, q, check=True):
                     lds[d:d + len(vals)] = vals
                     valid[d:d + len(vals)] = ok
                 e += cnt
-            for d, row, lim, k in ops[e:e + nstore]:
-                m = max(0, min(CHUNK * int(k), int(lim), H - int(s0)))
+            for d, row, lim, b in ops[e:e + nstore]:
+                m = max(0, min(CHUNK * K, int(lim), H - int(s0)))
+                vals, ok = lds[d:d + m], valid[d:d + m]
                 if check:
-                    assert d + CHUNK * k <= lds_n
-                    assert valid[d:d + m].all(), "a stored value depends on unloaded data"
-                dst[row, s0:s0 + m] = lds[d:d + m]
+                    assert 0 <= d and d + CHUNK * K <= lds_n
+                    assert (b >= 0) == store_merge
+                if store_merge:
+                    if check:
+                        assert b + CHUNK * K <= lds_n
+                    vals, ok = vals + lds[b:b + m], ok & valid[b:b + m]
+                if check:
+                    assert ok.all(), "a stored value depends on unloaded data"
+                dst[row, s0:s0 + m] = vals
                 written[row, s0:s0 + m] += 1
         if check:
             assert (written == 1).all(), f"pass {p} does not write every element exactly once"
