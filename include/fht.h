@@ -303,13 +303,19 @@ void fht_debug_fail_next(fht_status code, int32_t count);
  * fht_plan_num_passes returns the number of fused passes of view v (or -1).
  * fht_plan_pass_tables returns pointers into the plan (valid while it lives):
  *   hdrs  n_progs x FHT_HDR_INTS ints: [0] first entry, [1] loads, [2] stores,
- *         [3] steps, [4] LDS elements, [5] all entries, [6] level in,
- *         [7] height of the pass root, [8 + k] entries of step k,
- *         [24] first pass: end of the padded load windows, [25] positions per item
- *   ops   4 ints each, every entry covering k whole 64-position chunks:
+ *         [3] merge steps in LDS, [4] LDS elements, [5] all entries, [6] level in,
+ *         [7] height of the pass root, [8 + k] entries of LDS merge step k,
+ *         [24] first pass: end of the padded load windows, [25] positions per item,
+ *         [26] chunks k of every entry, [27] 1 if the stores add (the root's
+ *         last merge), [28] load-merges, [29] LDS element bytes
+ *   ops   4 ints each, every entry covering k whole 64-position chunks, in the
+ *         order loads, load-merges, merge steps, stores:
  *         load  {lds, src row, position offset, k}: lds[d+c] = src[row][(s0+off+c) mod H]
+ *         load-merge {lds dst, src row a, src row b, off | r << 16}:
+ *               lds[d+c] = src[a][(s0+off+c) mod H] + src[b][(s0+off+r+c) mod H]
  *         merge {lds dst, lds src0, lds src1, k}:  lds[d+c] = lds[a+c] + lds[b+c]
- *         store {lds, dst row, limit, k}: dst[row][s0+c] = lds[d+c], c < limit, s0+c < H
+ *         store {lds, dst row, limit, src1}: dst[row][s0+c] = lds[d+c] (+ lds[src1+c]
+ *               when [27] is set), c < limit, s0+c < H
  *   items 4 ints each: {program, 0, first position, 0}
  *   s_tile positions per item of this pass.
  */

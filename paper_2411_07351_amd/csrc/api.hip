@@ -1062,6 +1062,7 @@ fht_status fht_plan_work(fht_plan plan, int64_t *adds_tree, int64_t *adds_execut
                 int64_t merges = 0;
                 for (int k = 0; k < h[3]; ++k) merges += h[8 + k];
                 if (h[fht::kHdrStoreMerge]) merges += h[2];  // stores that add
+                merges += h[fht::kHdrLoadMerges];
                 done += merges * h[fht::kHdrChunks] * fht::kChunk;
             }
         }

@@ -199,6 +199,59 @@ __device__ __forceinline__ void load_rows_impl(TL *lds, const int4 *ent, int n, 
     }
 }
 
+// Load-merges {dst, row a, row b, offset | r << 16} (step 1 of a later pass,
+// read from the source rows instead of LDS copies of them):
+//   lds[dst + c] = src[a][(s0 + offset + c) mod H] + src[b][(s0 + offset + r + c) mod H]
+// Four entries' loads are in flight before their LDS writes.
+template <int K, int NW, typename TS, typename TL, bool ONE>
+__device__ __forceinline__ void load_merge_impl(TL *lds, const int4 *ent, int n, const TS *src,
+                                                int H, int s0, int wave, int lane)
+{
+    constexpr int R = 4;
+    for (int g = wave; g < n; g += 64 * NW) {
+        const int4 mine = fetch_desc<NW>(ent, n, g, lane);
+        const int m = group_size<NW>(n, g);
+        for (int j0 = 0; j0 < m; j0 += R) {
+            TS a[R][K], b[R][K];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int j = min(j0 + r, m - 1);
+                const uint32_t offs = static_cast<uint32_t>(rl(mine.w, j));
+                int ba = s0 + static_cast<int>(offs & 0xffffu);
+                if (ba >= H) ba %= H;
+                int bb = ba + static_cast<int>(offs >> 16);
+                if (bb >= H) bb %= H;
+                const TS *pa = src + static_cast<size_t>(rl(mine.y, j)) * H;
+                const TS *pb = src + static_cast<size_t>(rl(mine.z, j)) * H;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    a[r][k] = pa[static_cast<uint32_t>(wrap<ONE>(ba + 64 * k + lane, H))];
+                    b[r][k] = pb[static_cast<uint32_t>(wrap<ONE>(bb + 64 * k + lane, H))];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (j0 + r < m) {
+                    TL *dst = lds + rl(mine.x, j0 + r) + lane;
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+                        dst[64 * k] = static_cast<TL>(widen<TL>(a[r][k]) + widen<TL>(b[r][k]));
+                }
+            }
+        }
+    }
+}
+
+template <int K, int NW, typename TS, typename TL>
+__device__ __forceinline__ void load_merges(TL *lds, const int4 *ent, int n, const TS *src, int H,
+                                            int s0, int wave, int lane)
+{
+    if (H >= 64 * K)
+        load_merge_impl<K, NW, TS, TL, true>(lds, ent, n, src, H, s0, wave, lane);
+    else
+        load_merge_impl<K, NW, TS, TL, false>(lds, ent, n, src, H, s0, wave, lane);
+}
+
 template <int K, int NW, typename TS, typename TL>
 __device__ __forceinline__ void load_rows(TL *lds, const int4 *ent, int n, const TS *src, int H,
                                           int s0, int wave, int lane)
@@ -381,8 +434,13 @@ __device__ __forceinline__ void run_item(TL *lds, cptr<int32_t> hdr, const int4 
     const int nload = hdr[1], nstore = hdr[2], nsteps = hdr[3];
     const int H = job.H;
 
+    // load-merge entries: the planner emits them only for LDS elements of
+    // other than 4 bytes (4-byte rows are loaded straight into LDS instead)
+    constexpr bool LOAD_MERGE = !FROM_IMAGE && sizeof(TL) != 4;
+    const int nlm = LOAD_MERGE ? hdr[28] : 0;
+
     // Descriptors of the first merge step, fetched before the loads.
-    const int4 *step_ent = ent + nload;
+    const int4 *step_ent = ent + nload + nlm;
     int cnt = nsteps > 0 ? hdr[8] : 0;
     int4 cur = fetch_desc<NW>(step_ent, cnt, wave, lane);
 
@@ -392,6 +450,9 @@ __device__ __forceinline__ void run_item(TL *lds, cptr<int32_t> hdr, const int4 
     } else {
         load_rows<K, NW, TSrc, TL>(lds, ent, nload, reinterpret_cast<const TSrc *>(src), H, s0,
                                    wave, lane);
+        if constexpr (LOAD_MERGE)
+            load_merges<K, NW, TSrc, TL>(lds, ent + nload, nlm, reinterpret_cast<const TSrc *>(src),
+                                         H, s0, wave, lane);
         __builtin_amdgcn_s_waitcnt(0);  // direct-to-LDS loads have landed
     }
 

@@ -191,12 +191,16 @@ void collect_frontier(const Tree &tr, int ni, int level, std::vector<int> *out)
 // Entry formats (4 ints each):
 //   load   {lds row start, source row, position offset, K}; in the first
 //          pass there is one per lane, in lane order
+//   load-merge {lds dst, source row a, source row b, offset | r << 16}:
+//          lds[dst + c] = src[a][(s0 + offset + c) mod H]
+//                       + src[b][(s0 + offset + r + c) mod H]
+//          (step 1 of a later pass, read from the source rows)
 //   merge  {lds dst, lds src0, lds src1, K}
 //   store  {lds row start, destination row, position limit, lds src1 or -1}:
 //          with src1 >= 0 (every store of a program with merges) the stored
 //          value is lds[start + c] + lds[src1 + c], the root's last merge
 void emit_tile(const Tree &tr, int root, int ta, int tb, int lin, int S, int K, int pad,
-               Pass *pass)
+               bool load_merge, Pass *pass)
 {
     TileBuilder tb_{tr, lin, K, K * kChunk + pad, {}};
     const int rb = tb_.need(root, ta, tb - 1, 0, S);
@@ -204,6 +208,16 @@ void emit_tile(const Tree &tr, int root, int ta, int tb, int lin, int S, int K, 
     const int nsteps = std::max(0, tr.nodes[root].height - lin);
     bl[rb].last = nsteps + 1;
     bl[rb].virt = nsteps > 0;  // the stores compute it
+    // With load_merge, a later pass computes step 1 straight from the source
+    // rows (load-merges), so the rows only step 1 reads are never held in LDS.
+    // Offsets must fit the 16-bit fields of a load-merge entry.
+    bool fuse_loads = load_merge && lin > 0 && nsteps >= 2;
+    for (const Block &b : bl)
+        if (fuse_loads && b.step == 1 && (b.lo >= 65536 || b.hi + tr.nodes[b.node].w >= 65536))
+            fuse_loads = false;
+    if (fuse_loads)
+        for (Block &b : bl)
+            if (b.step == 0 && b.last == 1) b.virt = true;
     const int lds = place(bl);
 
     int32_t hdr[kHdrInts] = {0};
@@ -217,7 +231,7 @@ void emit_tile(const Tree &tr, int root, int ta, int tb, int lin, int S, int K, 
     int nload = 0, load_end = 0, widest = 0;
     for (const Block &b : bl) {
         widest = std::max(widest, b.width());
-        if (b.step != 0) continue;
+        if (b.step != 0 || b.virt) continue;
         const Node &n = tr.nodes[b.node];
         for (int u = b.ulo; u <= b.uhi; ++u, ++nload) {
             push(b.off + (u - b.ulo) * b.stride(), n.a + u, b.lo, K);
@@ -235,8 +249,27 @@ void emit_tile(const Tree &tr, int root, int ta, int tb, int lin, int S, int K, 
         return std::make_pair(L.off + (t0 - L.ulo) * L.stride() + (b.lo - L.lo),
                               R.off + (t1 - R.ulo) * R.stride() + (b.lo + r - R.lo));
     };
-    const int lds_steps = std::max(0, nsteps - 1);  // the last one is the stores'
-    for (int k = 1; k <= lds_steps; ++k) {
+    int nlm = 0;
+    if (fuse_loads) {
+        for (const Block &b : bl) {
+            if (b.step != 1) continue;
+            const Node &n = tr.nodes[b.node];
+            const Node &nl = tr.nodes[n.left], &nr = tr.nodes[n.right];
+            const int w = n.w, w0 = n.w0, w1 = w - w0;
+            for (int u = b.ulo; u <= b.uhi; ++u, ++nlm) {
+                const int t0 = static_cast<int>(round_half_even(int64_t(u) * (w0 - 1), w - 1));
+                const int t1 = static_cast<int>(round_half_even(int64_t(u) * (w1 - 1), w - 1));
+                const uint32_t offs = static_cast<uint32_t>(b.lo) |
+                                      (static_cast<uint32_t>(u - t1) << 16);
+                push(b.off + (u - b.ulo) * b.stride(), nl.a + t0, nr.a + t1,
+                     static_cast<int32_t>(offs));
+            }
+        }
+    }
+    // merge steps in LDS: all but the load-merged first and the stores' last
+    const int step0 = fuse_loads ? 2 : 1;
+    const int lds_steps = std::max(0, nsteps - step0);
+    for (int k = step0; k < step0 + lds_steps; ++k) {
         int cnt = 0;
         for (const Block &b : bl) {
             if (b.step != k) continue;
@@ -245,7 +278,7 @@ void emit_tile(const Tree &tr, int root, int ta, int tb, int lin, int S, int K, 
                 push(b.off + (u - b.ulo) * b.stride(), ab.first, ab.second, K);
             }
         }
-        hdr[8 + k - 1] = cnt;
+        hdr[8 + k - step0] = cnt;
     }
     int nstore = 0;
     {
@@ -272,6 +305,7 @@ void emit_tile(const Tree &tr, int root, int ta, int tb, int lin, int S, int K, 
     hdr[kHdrSTile] = S;
     hdr[kHdrChunks] = K;
     hdr[kHdrStoreMerge] = bl[rb].virt ? 1 : 0;
+    hdr[kHdrLoadMerges] = nlm;
     pass->hdrs.insert(pass->hdrs.end(), hdr, hdr + kHdrInts);
     pass->max_lds_elems = std::max(pass->max_lds_elems, lds);
     pass->widest = std::max(pass->widest, widest);
@@ -279,7 +313,7 @@ void emit_tile(const Tree &tr, int root, int ta, int tb, int lin, int S, int K, 
 }
 
 void build_pass(const Tree &tr, int lin, int lout, int T, int S, int K, int pad, int H,
-                Pass *pass)
+                bool load_merge, Pass *pass)
 {
     pass->lin = lin;
     pass->lout = lout;
@@ -293,7 +327,7 @@ void build_pass(const Tree &tr, int lin, int lout, int T, int S, int K, int pad,
         const int tt = (T <= 0) ? w : T;
         for (int ta = 0; ta < w; ta += tt) {
             const int prog = static_cast<int>(pass->hdrs.size() / kHdrInts);
-            emit_tile(tr, r, ta, std::min(w, ta + tt), lin, S, K, pad, pass);
+            emit_tile(tr, r, ta, std::min(w, ta + tt), lin, S, K, pad, load_merge, pass);
             for (int s0 = 0; s0 < H; s0 += S) {
                 pass->items.push_back(prog);
                 pass->items.push_back(0);
@@ -308,7 +342,7 @@ void build_pass(const Tree &tr, int lin, int lout, int T, int S, int K, int pad,
 // fits the target width (windows are the tile plus a spread that depends on
 // the slope tile only).
 void build_pass_fitted(const Tree &tr, int lin, int lout, int T, int target, int pad, int H,
-                       Pass *out)
+                       bool load_merge, Pass *out)
 {
     // Windows are S plus a spread that does not depend on S (nor on K): take
     // the widest window of every tile for S = 16, then pick the largest S.
@@ -327,7 +361,7 @@ void build_pass_fitted(const Tree &tr, int lin, int lout, int T, int target, int
     const int spread = widest - 16;
     const int S = std::min(H, std::max(16, target - spread));
     const int K = std::max(1, chunks_of(S + spread));
-    build_pass(tr, lin, lout, T, S, K, pad, H, out);
+    build_pass(tr, lin, lout, T, S, K, pad, H, load_merge, out);
 }
 
 }  // namespace
@@ -380,10 +414,15 @@ bool plan_axis(int W, int H, int split, const ElemRule &rule, const Schedule &sc
             } else {
                 tiles = {32, 16, 8, 4};
             }
+            // Load-merges pay off where rows reach LDS through registers anyway:
+            // 4-byte LDS elements are loaded straight from memory into LDS
+            // (cheaper than a second load per element), others are not.
+            const bool load_merge = eb != 4;
             for (int T : tiles) {
                 Pass p;
-                build_pass_fitted(tr, lin, lout, T, target, pad, H, &p);
+                build_pass_fitted(tr, lin, lout, T, target, pad, H, load_merge, &p);
                 p.elem_bytes = eb;
+                for (size_t h = 0; h < p.hdrs.size(); h += kHdrInts) p.hdrs[h + kHdrElemBytes] = eb;
                 if (p.fits && p.max_lds_elems <= budget_elems) {
                     best = std::move(p);
                     found = true;

@@ -5,7 +5,9 @@ them and checks the invariants the kernel relies on:
 
 * entries cover whole 64-position chunks: load ``lds[d + c] = src[row][(s0 +
   off + c) mod H]``, merge ``lds[d + c] = lds[a + c] + lds[b + c]`` for
-  ``c < 64 k``; store ``dst[row][s0 + c] = lds[d + c]`` (``+ lds[b + c]``
+  ``c < 64 k``; load-merge (step 1 of a later pass read from the source
+  rows) ``lds[d + c] = src[a][(s0 + off + c) mod H] + src[b][(s0 + off + r +
+  c) mod H]`` with ``off | r << 16`` in the entry's last field; store ``dst[row][s0 + c] = lds[d + c]`` (``+ lds[b + c]``
   when the header says the stores add the root's last merge) for
   ``c < min(64 k, limit)`` and ``s0 + c < H``;
 * every LDS access stays inside the program's footprint;
@@ -41,11 +43,11 @@ def run_plan_tables(plan_handle, img, q, check=True):
         for prog, _, s0, _ in tb["items"]:
             hdr = tb["hdrs"][prog]
             first, nload, nstore, nsteps, lds_n, nops = (int(x) for x in hdr[:6])
-            K, store_merge = int(hdr[26]), bool(hdr[27])
+            K, store_merge, nlm = int(hdr[26]), bool(hdr[27]), int(hdr[28])
             if check:
                 # programs with merges fold the last one into the stores
                 assert store_merge == (int(hdr[7]) > int(hdr[6]))
-            assert nops == nload + nstore + sum(int(c) for c in hdr[8:8 + nsteps])
+            assert nops == nload + nlm + nstore + sum(int(c) for c in hdr[8:8 + nsteps])
             assert int(hdr[25]) == tb["s_tile"]
             ops = tb["ops"][first:first + nops]
             lds = np.zeros(lds_n, dtype=src.dtype)
@@ -62,7 +64,23 @@ def run_plan_tables(plan_handle, img, q, check=True):
                 pos = (s0 + off + np.arange(n)) % H
                 lds[d:d + n] = src[row, pos]
                 valid[d:d + n] = True
-            e = nload
+            if check:
+                # load-merges only in later passes whose LDS elements are not 4 bytes
+                assert nlm == 0 or (int(hdr[6]) > 0 and int(hdr[29]) != 4)
+                spans = [(int(d), int(d) + CHUNK * K) for d, _, _, _ in ops[:nload + nlm]]
+                for i, a in enumerate(spans):
+                    assert 0 <= a[0] and a[1] <= lds_n
+                    assert not any(_overlap(a, b) for b in spans[i + 1:]), "loads overlap"
+            for d, ra, rb, offs in ops[nload:nload + nlm]:
+                offs = int(offs) & 0xFFFFFFFF
+                n = CHUNK * K
+                if check:
+                    assert 0 <= ra < W and 0 <= rb < W
+                pa = (s0 + (offs & 0xFFFF) + np.arange(n)) % H
+                pb = (s0 + (offs & 0xFFFF) + (offs >> 16) + np.arange(n)) % H
+                lds[d:d + n] = src[ra, pa] + src[rb, pb]
+                valid[d:d + n] = True
+            e = nload + nlm
             for step in range(nsteps):
                 cnt = int(hdr[8 + step])
                 step_ops = ops[e:e + cnt]
