@@ -94,7 +94,7 @@ struct Launch {
     Combo combo = Combo::I32_I32_I32;
     int lds_bytes = 0;
     int threads = 256;
-    std::vector<int32_t> items;  // {program, job slot, first position, 0}
+    std::vector<int32_t> items;  // {program, job slot, first position, first entry}
     std::vector<JobRef> jobs;    // plan launches: what each job slot runs
     std::string kernel;          // plan launches: the kernel's template signature
 };
@@ -175,6 +175,9 @@ struct ViewProgs {
             }
             ops.insert(ops.end(), ps.ops.begin(), ps.ops.end());
         }
+        // spare zero entries: the first pass fetches entries [first, first + 64)
+        // of a program before it knows the program's length
+        ops.resize(ops.size() + 4 * fht::kEntryPrefetch, 0);
         DevProgs x;
         x.device = d;
         int32_t *o = nullptr;
@@ -197,6 +200,14 @@ struct ViewProgs {
         int b = 0;
         for (size_t i = 0; i < p; ++i) b += static_cast<int>(plan.passes[i].hdrs.size() / fht::kHdrInts);
         return b;
+    }
+
+    // Device entry index of the first entry of program `prog` of pass p.
+    int first_entry(size_t p, int prog) const
+    {
+        int b = 0;
+        for (size_t i = 0; i < p; ++i) b += static_cast<int>(plan.passes[i].ops.size() / 4);
+        return b + plan.passes[p].hdrs[static_cast<size_t>(prog) * fht::kHdrInts];
     }
 };
 
@@ -608,7 +619,7 @@ void batch_prepare(fht_batch_s *b, const fht_plan *plans, int32_t n, const void 
                 dst[k4] = L.items[k4];
                 dst[k4 + 1] = slot0 + L.items[k4 + 1];
                 dst[k4 + 2] = L.items[k4 + 2];
-                dst[k4 + 3] = 0;
+                dst[k4 + 3] = L.items[k4 + 3];
             }
             B.lds_bytes = std::max(B.lds_bytes, L.lds_bytes);
         }
@@ -812,7 +823,7 @@ fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, fht_dtype 
                     L->items.push_back(items[i] + prog_base);
                     L->items.push_back(job);
                     L->items.push_back(items[i + 2]);
-                    L->items.push_back(0);
+                    L->items.push_back(p->view[v]->first_entry(l, items[i]));
                 }
                 L->lds_bytes = std::max(L->lds_bytes, ps.max_lds_elems * ps.elem_bytes);
             }

@@ -286,8 +286,16 @@ __device__ __forceinline__ TL image_elem(TSrc a, TSrc b)
         return static_cast<TL>(a);
 }
 
+// `pre` is entry `lane` of the program, fetched early (see fht_pass_kernel).
+__device__ __forceinline__ int4 lane_entry(const int4 &pre, int src_lane)
+{
+    const int a = src_lane << 2;
+    return make_int4(__builtin_amdgcn_ds_bpermute(a, pre.x), __builtin_amdgcn_ds_bpermute(a, pre.y),
+                     __builtin_amdgcn_ds_bpermute(a, pre.z), __builtin_amdgcn_ds_bpermute(a, pre.w));
+}
+
 template <int K, int NW, typename TSrc, typename TL, bool PAIR, bool ONE>
-__device__ __forceinline__ void load_image_impl(TL *lds, const int4 *ent, int nl, int load_end,
+__device__ __forceinline__ void load_image_impl(TL *lds, const int4 &pre, int nl, int load_end,
                                                 const TSrc *img, const JobDesc &job, int s0,
                                                 int wave, int lane)
 {
@@ -298,7 +306,7 @@ __device__ __forceinline__ void load_image_impl(TL *lds, const int4 *ent, int nl
         const int XW = nl <= 32 ? 32 : 64;
         const int x = threadIdx.x % XW, pstep = 64 * NW / XW;
         const bool xin = x < nl;
-        const int4 mine = ent[xin ? x : nl - 1];
+        const int4 mine = lane_entry(pre, xin ? x : nl - 1);
         const int wend = mine.z + 64 * K;
         const TSrc *colp = img + mine.y;
         constexpr int U = COLS_AT_ONCE;
@@ -320,7 +328,8 @@ __device__ __forceinline__ void load_image_impl(TL *lds, const int4 *ent, int nl
             }
         }
     } else {
-        const int4 mine = ent[lane < nl ? lane : nl - 1];
+        // lanes >= nl hold other entries; only lanes < nl are read (readlane)
+        const int4 mine = pre;
         // RW lanes per wavefront at a time (wavefront w takes lanes w + NW i)
         constexpr int RW = ROWS_AT_ONCE;
         for (int x0 = wave; x0 < nl; x0 += RW * NW) {
@@ -346,14 +355,14 @@ __device__ __forceinline__ void load_image_impl(TL *lds, const int4 *ent, int nl
 }
 
 template <int K, int NW, typename TSrc, typename TL, bool PAIR>
-__device__ __forceinline__ void load_image(TL *lds, const int4 *ent, int nl, int load_end,
+__device__ __forceinline__ void load_image(TL *lds, const int4 &pre, int nl, int load_end,
                                            const TSrc *img, const JobDesc &job, int s0, int wave,
                                            int lane)
 {
     if (load_end <= job.H)
-        load_image_impl<K, NW, TSrc, TL, PAIR, true>(lds, ent, nl, load_end, img, job, s0, wave, lane);
+        load_image_impl<K, NW, TSrc, TL, PAIR, true>(lds, pre, nl, load_end, img, job, s0, wave, lane);
     else
-        load_image_impl<K, NW, TSrc, TL, PAIR, false>(lds, ent, nl, load_end, img, job, s0, wave, lane);
+        load_image_impl<K, NW, TSrc, TL, PAIR, false>(lds, pre, nl, load_end, img, job, s0, wave, lane);
 }
 
 // Stores {src, row, limit, src1}: dst[row][s0 + c] = lds[src + c] for
@@ -425,8 +434,8 @@ __device__ __forceinline__ void store_rows(const TL *lds, const int4 *ent, int n
 
 template <int NT, int K, typename TSrc, typename TL, typename TD, bool FROM_IMAGE, bool PAIR>
 __device__ __forceinline__ void run_item(TL *lds, cptr<int32_t> hdr, const int4 *ent,
-                                         const JobDesc &job, const char *src, char *dst,
-                                         char *dst2, int s0)
+                                         const int4 &pre, const JobDesc &job, const char *src,
+                                         char *dst, char *dst2, int s0)
 {
     constexpr int NW = NT / 64;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -445,7 +454,7 @@ __device__ __forceinline__ void run_item(TL *lds, cptr<int32_t> hdr, const int4 
     int4 cur = fetch_desc<NW>(step_ent, cnt, wave, lane);
 
     if constexpr (FROM_IMAGE) {
-        load_image<K, NW, TSrc, TL, PAIR>(lds, ent, nload, hdr[24],
+        load_image<K, NW, TSrc, TL, PAIR>(lds, pre, nload, hdr[24],
                                           reinterpret_cast<const TSrc *>(src), job, s0, wave, lane);
     } else {
         load_rows<K, NW, TSrc, TL>(lds, ent, nload, reinterpret_cast<const TSrc *>(src), H, s0,
@@ -502,7 +511,13 @@ __global__ void __launch_bounds__(NT) fht_pass_kernel(PassArgs args, int n_items
     const E4 item = ld4(as_const(reinterpret_cast<const int32_t *>(args.items)), it);
     const JobDesc job = pick_job<TABLE>(args, item.y);
     cptr<int32_t> hdr = as_const(job.hdrs) + static_cast<size_t>(item.x) * 32;
-    const int4 *ent = job.ops + hdr[0];
+    // The item names its program's first entry, so the first pass fetches
+    // its load entries (one per lane of the root, at most 64) together with
+    // the header instead of after it; the tables end with spare entries, so
+    // this never reads past them.
+    const int4 *ent = job.ops + item.w;
+    int4 pre = make_int4(0, 0, 0, 0);
+    if constexpr (FROM_IMAGE) pre = ent[threadIdx.x & 63];
 
     const char *src = static_cast<const char *>(job.src);
     if (job.flags & JF_SRC_WS) src = args.ws + reinterpret_cast<uintptr_t>(job.src);
@@ -522,10 +537,10 @@ __global__ void __launch_bounds__(NT) fht_pass_kernel(PassArgs args, int n_items
     }
 
     switch (hdr[26]) {
-    case 1: run_item<NT, 1, TSrc, TL, TD, FROM_IMAGE, PAIR>(lds, hdr, ent, job, src, dst, dst2, item.z); break;
-    case 2: run_item<NT, 2, TSrc, TL, TD, FROM_IMAGE, PAIR>(lds, hdr, ent, job, src, dst, dst2, item.z); break;
-    case 3: run_item<NT, 3, TSrc, TL, TD, FROM_IMAGE, PAIR>(lds, hdr, ent, job, src, dst, dst2, item.z); break;
-    default: run_item<NT, 4, TSrc, TL, TD, FROM_IMAGE, PAIR>(lds, hdr, ent, job, src, dst, dst2, item.z); break;
+    case 1: run_item<NT, 1, TSrc, TL, TD, FROM_IMAGE, PAIR>(lds, hdr, ent, pre, job, src, dst, dst2, item.z); break;
+    case 2: run_item<NT, 2, TSrc, TL, TD, FROM_IMAGE, PAIR>(lds, hdr, ent, pre, job, src, dst, dst2, item.z); break;
+    case 3: run_item<NT, 3, TSrc, TL, TD, FROM_IMAGE, PAIR>(lds, hdr, ent, pre, job, src, dst, dst2, item.z); break;
+    default: run_item<NT, 4, TSrc, TL, TD, FROM_IMAGE, PAIR>(lds, hdr, ent, pre, job, src, dst, dst2, item.z); break;
     }
 }
 

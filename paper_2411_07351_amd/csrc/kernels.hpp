@@ -33,7 +33,7 @@ enum : int32_t {
 constexpr int kInlineJobs = 4;
 
 struct PassArgs {
-    const int4 *items;     // {program of the job's view, job, first position, 0}
+    const int4 *items;     // {program of the job's view, job, first position, first entry}
     const JobDesc *jobs;   // device job table, or null to use inl
     char *ws;              // workspace base for JF_*_WS offsets
     // Same-shape image batches (grid.y = image b, inline jobs only): image b's

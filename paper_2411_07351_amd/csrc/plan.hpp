@@ -20,6 +20,7 @@ constexpr int kChunk = 64;       // positions per chunk (one wavefront access)
 constexpr int kMaxFirstLevels = 6;  // first-pass roots have at most 64 lanes
 constexpr int kMaxTarget = 256;     // widest row window a schedule may ask for
 constexpr int kMaxChunks = 4;       // chunks per entry the kernels are built for
+constexpr int kEntryPrefetch = 64;  // entries a kernel may read from a program's first one
 
 // [.] of Alg. 1: nearest integer to num / den (num >= 0, den > 0), ties to even.
 int64_t round_half_even(int64_t num, int64_t den);
