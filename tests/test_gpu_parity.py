@@ -226,3 +226,33 @@ def test_forward_many_equals_single_images(F, kind, shape, n):
         plan.forward(imgs[b], solo)
         torch.cuda.synchronize()
         assert torch.equal(outs[b], solo), b
+
+
+@pytest.mark.parametrize("kind", ["u8", "f32", "f64"])
+def test_random_shapes_every_path(F, kind):
+    # Seeded shapes, log-uniform per side up to 1100 lanes, plus shapes whose
+    # widening pass fuses two levels (513..1024 lanes), and quadrant subsets
+    # (views without a quadrant pair): every pass kind of the planner (loads,
+    # load-merges, merge steps, stores that add) against the C oracle.
+    rng = WL.rng_for(6, salt={"u8": 1, "f32": 2, "f64": 3}[kind])
+    sides = np.exp(rng.uniform(0.0, np.log(1100.0), size=(6, 2))).astype(int)
+    shapes = [tuple(int(v) for v in rc) for rc in sides] + [(700, 90), (90, 700), (1021, 3)]
+    subsets = [(0, 1, 2, 3), (0,), (3,), (1, 2)]
+    for i, (R, C) in enumerate(shapes):
+        split = i % 2
+        qs = subsets[i % len(subsets)]
+        if kind == "u8":
+            img = WL.uniform_u8(rng, R, C)
+            got = _gpu_hough(F, img, split, quadrants=qs)
+            ref = native.hough4_u8(img, split)
+            for g, q in zip(got, qs):
+                assert g.dtype == np.int32 and (g == ref[q]).all(), (R, C, split, q)
+        else:
+            img = WL.normal_f32(rng, R, C)
+            if kind == "f64":
+                img = img.astype(np.float64)
+            got = _gpu_hough(F, img, split, quadrants=qs)
+            ref, ab = native.hough4_f64(img.astype(np.float64), split)
+            tol = 1e-5 if kind == "f32" else 1e-12
+            for g, q in zip(got, qs):
+                _assert_float_close(g, ref[q], ab[q], tol)
