@@ -39,8 +39,10 @@ __global__ void __launch_bounds__(256) adj_step_kernel(AdjArgs args)
     // load and are broadcast with readlane, so no load waits per term.
     const int m0 = min(64, t1 - t0);
     const int2 first = lane < m0 ? job.terms[t0 + lane] : make_int2(0, 0);
-    // four terms times four 64-position chunks of loads in flight together
+    // four terms times up to four 64-position chunks of loads in flight
+    // together; the last group of a row takes only the chunks it covers
     for (int s0 = 0; s0 < H; s0 += 256) {
+        const int nu = min(4, (H - s0 + 63) >> 6);
         T acc[4] = {T(0), T(0), T(0), T(0)};
         for (int tb = t0; tb < t1; tb += 64) {
             const int m = min(64, t1 - tb);
@@ -55,6 +57,7 @@ __global__ void __launch_bounds__(256) adj_step_kernel(AdjArgs args)
                     const T *row = src + static_cast<size_t>(rowi) * H;
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
+                        if (u >= nu) break;
                         const int s = min(s0 + 64 * u + lane, H - 1);
                         int y = s - sh;
                         if (y < 0) y += H;
@@ -66,7 +69,8 @@ __global__ void __launch_bounds__(256) adj_step_kernel(AdjArgs args)
                 for (int jj = 0; jj < 4; ++jj)
                     if (j0 + jj < m) {
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) acc[u] += v[jj][u];
+                        for (int u = 0; u < 4; ++u)
+                            if (u < nu) acc[u] += v[jj][u];
                     }
             }
         }
