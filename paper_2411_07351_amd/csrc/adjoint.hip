@@ -19,6 +19,7 @@ namespace fht {
 namespace {
 
 constexpr int kRowsPerBlock = 4;  // one wavefront per output row
+constexpr int kTermsAtOnce = 8;   // terms whose loads are in flight together
 
 template <typename T>
 __global__ void __launch_bounds__(256) adj_step_kernel(AdjArgs args)
@@ -39,18 +40,19 @@ __global__ void __launch_bounds__(256) adj_step_kernel(AdjArgs args)
     // load and are broadcast with readlane, so no load waits per term.
     const int m0 = min(64, t1 - t0);
     const int2 first = lane < m0 ? job.terms[t0 + lane] : make_int2(0, 0);
-    // four terms times up to four 64-position chunks of loads in flight
-    // together; the last group of a row takes only the chunks it covers
+    // eight terms times up to four 64-position chunks of loads in flight
+    // together (three fused levels give about eight terms per row); the last
+    // group of a row takes only the chunks it covers
     for (int s0 = 0; s0 < H; s0 += 256) {
         const int nu = min(4, (H - s0 + 63) >> 6);
         T acc[4] = {T(0), T(0), T(0), T(0)};
         for (int tb = t0; tb < t1; tb += 64) {
             const int m = min(64, t1 - tb);
             const int2 mine = tb == t0 ? first : (lane < m ? job.terms[tb + lane] : make_int2(0, 0));
-            for (int j0 = 0; j0 < m; j0 += 4) {
-                T v[4][4];
+            for (int j0 = 0; j0 < m; j0 += kTermsAtOnce) {
+                T v[kTermsAtOnce][4];
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
+                for (int jj = 0; jj < kTermsAtOnce; ++jj) {
                     const int j = min(j0 + jj, m - 1);
                     const int rowi = __builtin_amdgcn_readlane(mine.x, j);
                     const int sh = __builtin_amdgcn_readlane(mine.y, j);
@@ -66,7 +68,7 @@ __global__ void __launch_bounds__(256) adj_step_kernel(AdjArgs args)
                     }
                 }
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj)
+                for (int jj = 0; jj < kTermsAtOnce; ++jj)
                     if (j0 + jj < m) {
 #pragma unroll
                         for (int u = 0; u < 4; ++u)
@@ -92,48 +94,59 @@ template <typename T>
 __global__ void __launch_bounds__(256) adj_combine_kernel(CombineArgs args)
 {
     __shared__ T tile[kTile][kTile + 1];
+    constexpr int KR = kTile / 4;  // rows per thread
     const int R = args.R, C = args.C;
     const int i0 = blockIdx.y * kTile, j0 = blockIdx.x * kTile;
     const int tj = threadIdx.x & 63, ti = threadIdx.x >> 6;  // 64 x 4 threads
-    T acc[kTile / 4];
-#pragma unroll
-    for (int k = 0; k < kTile / 4; ++k) acc[k] = T(0);
-    const int j = j0 + tj;
     const int64_t b = blockIdx.z;  // image of a same-shape batch
-    for (int q = 0; q < 2; ++q) {
-        const T *g = args.src[q] ? reinterpret_cast<const T *>(static_cast<const char *>(args.src[q]) +
-                                                               b * args.src_stride[q])
-                                 : nullptr;
-        if (!g || j >= C) continue;
-        const int jj = (args.mirror[q] && j != 0) ? C - j : j;
+    auto source = [&](int q) -> const T * {
+        return args.src[q] ? reinterpret_cast<const T *>(static_cast<const char *>(args.src[q]) +
+                                                         b * args.src_stride[q])
+                           : nullptr;
+    };
+    // Row-lane quadrants: every load of the thread is issued before the adds.
+    const T *g0 = source(0), *g1 = source(1);
+    const int j = j0 + tj;
+    T acc[KR];
+    {
+        const int jc = min(j, C - 1);
+        const int jj0 = (args.mirror[0] && jc != 0) ? C - jc : jc;
+        const int jj1 = (args.mirror[1] && jc != 0) ? C - jc : jc;
+        T v0[KR], v1[KR];
 #pragma unroll
-        for (int k = 0; k < kTile / 4; ++k) {
-            const int i = i0 + ti + 4 * k;
-            if (i < R) acc[k] += g[static_cast<size_t>(i) * C + jj];
+        for (int k = 0; k < KR; ++k) {
+            const size_t row = static_cast<size_t>(min(i0 + ti + 4 * k, R - 1)) * C;
+            v0[k] = g0 ? g0[row + jj0] : T(0);
+            v1[k] = g1 ? g1[row + jj1] : T(0);
         }
+#pragma unroll
+        for (int k = 0; k < KR; ++k) acc[k] = v0[k] + v1[k];
     }
-    for (int q = 2; q < 4; ++q) {
-        const T *g = args.src[q] ? reinterpret_cast<const T *>(static_cast<const char *>(args.src[q]) +
-                                                               b * args.src_stride[q])
-                                 : nullptr;
-        if (!g) continue;  // uniform across the block
-        // stage g[j0 + a][i'(i0 + b)] as tile[a][b], threads along b
-        const int b = threadIdx.x & 63;
-        const int i = i0 + b;
-        const int ii = (args.mirror[q] && i != 0) ? R - i : i;
-        for (int a = threadIdx.x >> 6; a < kTile; a += 4) {
-            const int jr = j0 + a;
-            tile[a][b] = (jr < C && i < R) ? g[static_cast<size_t>(jr) * R + ii] : T(0);
+    // Column-lane quadrants: both are staged, summed, as tile[a][c] =
+    // g[j0 + a][i'(i0 + c)] with threads along c, then read transposed.
+    const T *g2 = source(2), *g3 = source(3);
+    if (g2 || g3) {  // uniform across the block
+        const int c = threadIdx.x & 63;
+        const int i = min(i0 + c, R - 1);
+        const int ii2 = (args.mirror[2] && i != 0) ? R - i : i;
+        const int ii3 = (args.mirror[3] && i != 0) ? R - i : i;
+        T v2[KR], v3[KR];
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+            const size_t row = static_cast<size_t>(min(j0 + ti + 4 * k, C - 1)) * R;
+            v2[k] = g2 ? g2[row + ii2] : T(0);
+            v3[k] = g3 ? g3[row + ii3] : T(0);
         }
+#pragma unroll
+        for (int k = 0; k < KR; ++k) tile[ti + 4 * k][c] = v2[k] + v3[k];
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < kTile / 4; ++k) acc[k] += tile[tj][ti + 4 * k];
-        __syncthreads();
+        for (int k = 0; k < KR; ++k) acc[k] += tile[tj][ti + 4 * k];
     }
     T *out = reinterpret_cast<T *>(static_cast<char *>(args.dst) + b * args.dst_stride);
     if (j < C) {
 #pragma unroll
-        for (int k = 0; k < kTile / 4; ++k) {
+        for (int k = 0; k < KR; ++k) {
             const int i = i0 + ti + 4 * k;
             if (i < R) out[static_cast<size_t>(i) * C + j] = acc[k];
         }
