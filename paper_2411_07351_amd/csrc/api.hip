@@ -819,6 +819,7 @@ fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, fht_dtype 
                 }
                 const int job = static_cast<int>(L->jobs.size());
                 L->jobs.push_back(JobRef{q, pair});
+                L->items.reserve(L->items.size() + items.size());
                 for (size_t i = 0; i < items.size(); i += 4) {
                     L->items.push_back(items[i] + prog_base);
                     L->items.push_back(job);

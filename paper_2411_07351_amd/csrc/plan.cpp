@@ -27,7 +27,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
-#include <numeric>
+#include <map>
 
 namespace fht {
 
@@ -107,12 +107,46 @@ struct Block {
     int size() const { return virt ? 0 : rows() * stride() + overrun; }
 };
 
+struct Live { int off, size, last; };
+
+// State shared by the tile builds of one axis plan: the child rows t0, t1 of
+// every row u of every non-leaf node, computed once per distinct (w, w0) of
+// the tree (rows(n)[2 u], rows(n)[2 u + 1]), and buffers reused from one
+// tile to the next.
+struct PlanWork {
+    const Tree &tr;
+    std::map<std::pair<int, int>, std::vector<int32_t>> by_width;
+    std::vector<const int32_t *> by_node;
+    std::vector<Block> blocks;
+    std::vector<int> order;
+    std::vector<Live> live;
+
+    explicit PlanWork(const Tree &t) : tr(t), by_node(t.nodes.size(), nullptr) {}
+
+    const int32_t *rows(int ni)
+    {
+        if (by_node[ni]) return by_node[ni];
+        const Node &n = tr.nodes[ni];
+        const int w = n.w, w0 = n.w0, w1 = w - w0;
+        std::vector<int32_t> &v = by_width[{w, w0}];
+        if (v.empty()) {
+            v.resize(2 * static_cast<size_t>(w));
+            for (int u = 0; u < w; ++u) {
+                v[2 * u] = static_cast<int32_t>(round_half_even(int64_t(u) * (w0 - 1), w - 1));
+                v[2 * u + 1] = static_cast<int32_t>(round_half_even(int64_t(u) * (w1 - 1), w - 1));
+            }
+        }
+        return by_node[ni] = v.data();
+    }
+};
+
 struct TileBuilder {
     const Tree &tr;
+    PlanWork &work;
     int lin;
-    int K;            // chunks every entry of the tile covers
-    int stride;       // LDS row stride: K chunks plus a bank-skew pad
-    std::vector<Block> blocks;
+    int K;                       // chunks every entry of the tile covers
+    int stride;                  // LDS row stride: K chunks plus a bank-skew pad
+    std::vector<Block> &blocks;  // cleared by the caller
 
     int need(int ni, int ulo, int uhi, int lo, int hi)
     {
@@ -122,11 +156,9 @@ struct TileBuilder {
         blocks[b].row_stride = stride;
         if (n.height <= lin) return b;
         blocks[b].step = n.height - lin;
-        const int w = n.w, w0 = n.w0, w1 = w - w0;
-        const int t0lo = static_cast<int>(round_half_even(int64_t(ulo) * (w0 - 1), w - 1));
-        const int t0hi = static_cast<int>(round_half_even(int64_t(uhi) * (w0 - 1), w - 1));
-        const int t1lo = static_cast<int>(round_half_even(int64_t(ulo) * (w1 - 1), w - 1));
-        const int t1hi = static_cast<int>(round_half_even(int64_t(uhi) * (w1 - 1), w - 1));
+        const int32_t *tt = work.rows(ni);
+        const int t0lo = tt[2 * ulo], t0hi = tt[2 * uhi];
+        const int t1lo = tt[2 * ulo + 1], t1hi = tt[2 * uhi + 1];
         const int lb = need(n.left, t0lo, t0hi, lo, hi);
         const int rb = need(n.right, t1lo, t1hi, lo + (ulo - t1lo), hi + (uhi - t1hi));
         blocks[lb].last = blocks[b].step;
@@ -144,21 +176,24 @@ struct TileBuilder {
 
 // First-fit placement of the blocks in LDS; a block may reuse the space of
 // blocks whose last reader ran in an earlier step.  Returns the footprint.
-int place(std::vector<Block> &blocks)
+int place(std::vector<Block> &blocks, PlanWork &work)
 {
-    std::vector<int> order(blocks.size());
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int x, int y) { return blocks[x].step < blocks[y].step; });
-    struct Live { int off, size, last; };
-    std::vector<Live> live;
+    // blocks in step order, in index order within a step
+    std::vector<int> &order = work.order;
+    order.clear();
+    int max_step = 0;
+    for (const Block &b : blocks) max_step = std::max(max_step, b.step);
+    for (int st = 0; st <= max_step; ++st)
+        for (size_t i = 0; i < blocks.size(); ++i)
+            if (blocks[i].step == st) order.push_back(static_cast<int>(i));
+    std::vector<Live> &live = work.live;  // kept in offset order
+    live.clear();
     int top = 0;
     for (int b : order) {
         Block &blk = blocks[b];
         live.erase(std::remove_if(live.begin(), live.end(),
                                   [&](const Live &l) { return l.last < blk.step; }),
                    live.end());
-        std::sort(live.begin(), live.end(), [](const Live &x, const Live &y) { return x.off < y.off; });
         const int size = blk.size();
         int pos = 0;
         for (const Live &l : live) {
@@ -166,7 +201,9 @@ int place(std::vector<Block> &blocks)
             pos = std::max(pos, l.off + l.size);
         }
         blk.off = pos;
-        live.push_back(Live{pos, size, blk.last});
+        const auto at = std::upper_bound(live.begin(), live.end(), pos,
+                                         [](int off, const Live &l) { return off < l.off; });
+        live.insert(at, Live{pos, size, blk.last});
         top = std::max(top, pos + size);
     }
     return top;
@@ -199,10 +236,11 @@ void collect_frontier(const Tree &tr, int ni, int level, std::vector<int> *out)
 //   store  {lds row start, destination row, position limit, lds src1 or -1}:
 //          with src1 >= 0 (every store of a program with merges) the stored
 //          value is lds[start + c] + lds[src1 + c], the root's last merge
-void emit_tile(const Tree &tr, int root, int ta, int tb, int lin, int S, int K, int pad,
-               bool load_merge, Pass *pass)
+void emit_tile(const Tree &tr, PlanWork &work, int root, int ta, int tb, int lin, int S, int K,
+               int pad, bool load_merge, Pass *pass)
 {
-    TileBuilder tb_{tr, lin, K, K * kChunk + pad, {}};
+    work.blocks.clear();
+    TileBuilder tb_{tr, work, lin, K, K * kChunk + pad, work.blocks};
     const int rb = tb_.need(root, ta, tb - 1, 0, S);
     std::vector<Block> &bl = tb_.blocks;
     const int nsteps = std::max(0, tr.nodes[root].height - lin);
@@ -218,7 +256,7 @@ void emit_tile(const Tree &tr, int root, int ta, int tb, int lin, int S, int K, 
     if (fuse_loads)
         for (Block &b : bl)
             if (b.step == 0 && b.last == 1) b.virt = true;
-    const int lds = place(bl);
+    const int lds = place(bl, work);
 
     int32_t hdr[kHdrInts] = {0};
     const int first = static_cast<int>(pass->ops.size() / 4);
@@ -240,11 +278,9 @@ void emit_tile(const Tree &tr, int root, int ta, int tb, int lin, int S, int K, 
     }
     // LDS offsets of the two operands of row u of computed block b
     auto operands = [&](const Block &b, int u) {
-        const Node &n = tr.nodes[b.node];
         const Block &L = bl[b.lb], &R = bl[b.rb];
-        const int w = n.w, w0 = n.w0, w1 = w - w0;
-        const int t0 = static_cast<int>(round_half_even(int64_t(u) * (w0 - 1), w - 1));
-        const int t1 = static_cast<int>(round_half_even(int64_t(u) * (w1 - 1), w - 1));
+        const int32_t *tt = work.rows(b.node);
+        const int t0 = tt[2 * u], t1 = tt[2 * u + 1];
         const int r = u - t1;
         return std::make_pair(L.off + (t0 - L.ulo) * L.stride() + (b.lo - L.lo),
                               R.off + (t1 - R.ulo) * R.stride() + (b.lo + r - R.lo));
@@ -255,10 +291,9 @@ void emit_tile(const Tree &tr, int root, int ta, int tb, int lin, int S, int K, 
             if (b.step != 1) continue;
             const Node &n = tr.nodes[b.node];
             const Node &nl = tr.nodes[n.left], &nr = tr.nodes[n.right];
-            const int w = n.w, w0 = n.w0, w1 = w - w0;
+            const int32_t *tt = work.rows(b.node);
             for (int u = b.ulo; u <= b.uhi; ++u, ++nlm) {
-                const int t0 = static_cast<int>(round_half_even(int64_t(u) * (w0 - 1), w - 1));
-                const int t1 = static_cast<int>(round_half_even(int64_t(u) * (w1 - 1), w - 1));
+                const int t0 = tt[2 * u], t1 = tt[2 * u + 1];
                 const uint32_t offs = static_cast<uint32_t>(b.lo) |
                                       (static_cast<uint32_t>(u - t1) << 16);
                 push(b.off + (u - b.ulo) * b.stride(), nl.a + t0, nr.a + t1,
@@ -312,8 +347,8 @@ void emit_tile(const Tree &tr, int root, int ta, int tb, int lin, int S, int K, 
     if (widest > K * kChunk || K > kMaxChunks) pass->fits = false;
 }
 
-void build_pass(const Tree &tr, int lin, int lout, int T, int S, int K, int pad, int H,
-                bool load_merge, Pass *pass)
+void build_pass(const Tree &tr, PlanWork &work, int lin, int lout, int T, int S, int K,
+                int pad, int H, bool load_merge, Pass *pass)
 {
     pass->lin = lin;
     pass->lout = lout;
@@ -327,7 +362,7 @@ void build_pass(const Tree &tr, int lin, int lout, int T, int S, int K, int pad,
         const int tt = (T <= 0) ? w : T;
         for (int ta = 0; ta < w; ta += tt) {
             const int prog = static_cast<int>(pass->hdrs.size() / kHdrInts);
-            emit_tile(tr, r, ta, std::min(w, ta + tt), lin, S, K, pad, load_merge, pass);
+            emit_tile(tr, work, r, ta, std::min(w, ta + tt), lin, S, K, pad, load_merge, pass);
             for (int s0 = 0; s0 < H; s0 += S) {
                 pass->items.push_back(prog);
                 pass->items.push_back(0);
@@ -341,8 +376,8 @@ void build_pass(const Tree &tr, int lin, int lout, int T, int S, int K, int pad,
 // Builds the pass with the largest position tile whose widest window still
 // fits the target width (windows are the tile plus a spread that depends on
 // the slope tile only).
-void build_pass_fitted(const Tree &tr, int lin, int lout, int T, int target, int pad, int H,
-                       bool load_merge, Pass *out)
+void build_pass_fitted(const Tree &tr, PlanWork &work, int lin, int lout, int T, int target,
+                       int pad, int H, bool load_merge, Pass *out)
 {
     // Windows are S plus a spread that does not depend on S (nor on K): take
     // the widest window of every tile for S = 16, then pick the largest S.
@@ -353,7 +388,8 @@ void build_pass_fitted(const Tree &tr, int lin, int lout, int T, int target, int
         const int w = tr.nodes[r].w;
         const int tt = (T <= 0) ? w : T;
         for (int ta = 0; ta < w; ta += tt) {
-            TileBuilder probe{tr, lin, 1, kChunk, {}};
+            work.blocks.clear();
+            TileBuilder probe{tr, work, lin, 1, kChunk, work.blocks};
             probe.need(r, ta, std::min(w, ta + tt) - 1, 0, 16);
             for (const Block &b : probe.blocks) widest = std::max(widest, b.width());
         }
@@ -361,7 +397,7 @@ void build_pass_fitted(const Tree &tr, int lin, int lout, int T, int target, int
     const int spread = widest - 16;
     const int S = std::min(H, std::max(16, target - spread));
     const int K = std::max(1, chunks_of(S + spread));
-    build_pass(tr, lin, lout, T, S, K, pad, H, load_merge, out);
+    build_pass(tr, work, lin, lout, T, S, K, pad, H, load_merge, out);
 }
 
 }  // namespace
@@ -385,6 +421,7 @@ bool plan_axis(int W, int H, int split, const ElemRule &rule, const Schedule &sc
         return false;
     }
     const Tree tr = make_tree(W, split);
+    PlanWork work(tr);
     const int L = tr.nodes[0].height;
     out->W = W;
     out->H = H;
@@ -420,7 +457,7 @@ bool plan_axis(int W, int H, int split, const ElemRule &rule, const Schedule &sc
             const bool load_merge = eb != 4;
             for (int T : tiles) {
                 Pass p;
-                build_pass_fitted(tr, lin, lout, T, target, pad, H, load_merge, &p);
+                build_pass_fitted(tr, work, lin, lout, T, target, pad, H, load_merge, &p);
                 p.elem_bytes = eb;
                 for (size_t h = 0; h < p.hdrs.size(); h += kHdrInts) p.hdrs[h + kHdrElemBytes] = eb;
                 if (p.fits && p.max_lds_elems <= budget_elems) {
