@@ -1072,8 +1072,8 @@ fht_status fht_plan_work(fht_plan plan, int64_t *adds_tree, int64_t *adds_execut
             for (size_t i = 0; i < items.size(); i += 4) {
                 const int32_t *h = ps.hdrs.data() + static_cast<size_t>(items[i]) * fht::kHdrInts;
                 int64_t merges = 0;
-                for (int k = 0; k < h[3]; ++k) merges += h[8 + k];
-                if (h[fht::kHdrStoreMerge]) merges += h[2];  // stores that add
+                for (int k = 0; k < h[fht::kHdrSteps]; ++k) merges += h[fht::kHdrStepCounts + k];
+                if (h[fht::kHdrStoreMerge]) merges += h[fht::kHdrStores];  // stores that add
                 merges += h[fht::kHdrLoadMerges];
                 done += merges * h[fht::kHdrChunks] * fht::kChunk;
             }

@@ -4,7 +4,11 @@
 // item (one workgroup of 4 or 8 wavefronts) runs a planner-made program:
 // it loads the rows its slope tile needs into LDS, runs the merge steps of
 // Alg. 1 (row t of a node = row t0 of the left child + row t1 of the right
-// child rotated by t - t1) entirely in LDS, and writes its output rows back.
+// child rotated by t - t1) in LDS, and writes its output rows back.  The
+// stores do the root's last merge on the way out, and a pass whose rows reach
+// LDS through registers does its first merge on the way in (load-merges), so
+// neither level's rows pass through LDS: LDS writes are the scarcest LDS
+// bandwidth on this chip.
 // The rotation is folded into LDS addresses, so every merge is a contiguous
 // vector add over K whole 64-position chunks: one position per lane, which
 // keeps LDS accesses bank-conflict free and HBM accesses coalesced.  This is
@@ -18,6 +22,7 @@
 // runs.  Later passes load HBM rows straight into LDS (global_load_lds_dword),
 // all of a wavefront's rows in flight at once.
 #include "kernels.hpp"
+#include "plan.hpp"  // program header layout (host and device agree on it)
 
 #include <type_traits>
 
@@ -440,21 +445,21 @@ __device__ __forceinline__ void run_item(TL *lds, cptr<int32_t> hdr, const int4 
     constexpr int NW = NT / 64;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int nload = hdr[1], nstore = hdr[2], nsteps = hdr[3];
+    const int nload = hdr[kHdrLoads], nstore = hdr[kHdrStores], nsteps = hdr[kHdrSteps];
     const int H = job.H;
 
     // load-merge entries: the planner emits them only for LDS elements of
     // other than 4 bytes (4-byte rows are loaded straight into LDS instead)
     constexpr bool LOAD_MERGE = !FROM_IMAGE && sizeof(TL) != 4;
-    const int nlm = LOAD_MERGE ? hdr[28] : 0;
+    const int nlm = LOAD_MERGE ? hdr[kHdrLoadMerges] : 0;
 
     // Descriptors of the first merge step, fetched before the loads.
     const int4 *step_ent = ent + nload + nlm;
-    int cnt = nsteps > 0 ? hdr[8] : 0;
+    int cnt = nsteps > 0 ? hdr[kHdrStepCounts] : 0;
     int4 cur = fetch_desc<NW>(step_ent, cnt, wave, lane);
 
     if constexpr (FROM_IMAGE) {
-        load_image<K, NW, TSrc, TL, PAIR>(lds, pre, nload, hdr[24],
+        load_image<K, NW, TSrc, TL, PAIR>(lds, pre, nload, hdr[kHdrLoadEnd],
                                           reinterpret_cast<const TSrc *>(src), job, s0, wave, lane);
     } else {
         load_rows<K, NW, TSrc, TL>(lds, ent, nload, reinterpret_cast<const TSrc *>(src), H, s0,
@@ -468,7 +473,7 @@ __device__ __forceinline__ void run_item(TL *lds, cptr<int32_t> hdr, const int4 
     for (int k = 0; k < nsteps; ++k) {
         __syncthreads();
         const int4 *next_ent = step_ent + cnt;
-        const int next_cnt = k + 1 < nsteps ? hdr[8 + k + 1] : 0;
+        const int next_cnt = k + 1 < nsteps ? hdr[kHdrStepCounts + k + 1] : 0;
         const int4 nxt = fetch_desc<NW>(next_ent, next_cnt, wave, lane);
         if (wave < cnt) merge_group<K, TL>(lds, cur, group_size<NW>(cnt, wave), lane);
         for (int g = wave + 64 * NW; g < cnt; g += 64 * NW)
@@ -482,7 +487,7 @@ __device__ __forceinline__ void run_item(TL *lds, cptr<int32_t> hdr, const int4 
 
     constexpr bool PAIR_OUT = PAIR && sizeof(TD) == 4 && std::is_signed<TD>::value;
     const bool unmirror = (job.flags & JF_FINAL) && (PAIR_OUT || (job.flags & JF_MIRROR));
-    if (hdr[27])  // the stores add the root's last merge
+    if (hdr[kHdrStoreMerge])  // the stores add the root's last merge
         store_rows<K, NW, TL, TD, PAIR_OUT, true>(lds, step_ent, nstore, reinterpret_cast<TD *>(dst),
                                                   reinterpret_cast<TD *>(dst2), H, s0, unmirror,
                                                   wave, lane);
@@ -510,7 +515,7 @@ __global__ void __launch_bounds__(NT) fht_pass_kernel(PassArgs args, int n_items
     if (it >= n_items) return;
     const E4 item = ld4(as_const(reinterpret_cast<const int32_t *>(args.items)), it);
     const JobDesc job = pick_job<TABLE>(args, item.y);
-    cptr<int32_t> hdr = as_const(job.hdrs) + static_cast<size_t>(item.x) * 32;
+    cptr<int32_t> hdr = as_const(job.hdrs) + static_cast<size_t>(item.x) * kHdrInts;
     // The item names its program's first entry, so the first pass fetches
     // its load entries (one per lane of the root, at most 64) together with
     // the header instead of after it; the tables end with spare entries, so
@@ -536,7 +541,7 @@ __global__ void __launch_bounds__(NT) fht_pass_kernel(PassArgs args, int n_items
         dst2 += od;
     }
 
-    switch (hdr[26]) {
+    switch (hdr[kHdrChunks]) {
     case 1: run_item<NT, 1, TSrc, TL, TD, FROM_IMAGE, PAIR>(lds, hdr, ent, pre, job, src, dst, dst2, item.z); break;
     case 2: run_item<NT, 2, TSrc, TL, TD, FROM_IMAGE, PAIR>(lds, hdr, ent, pre, job, src, dst, dst2, item.z); break;
     case 3: run_item<NT, 3, TSrc, TL, TD, FROM_IMAGE, PAIR>(lds, hdr, ent, pre, job, src, dst, dst2, item.z); break;

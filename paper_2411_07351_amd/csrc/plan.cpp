@@ -313,7 +313,7 @@ void emit_tile(const Tree &tr, PlanWork &work, int root, int ta, int tb, int lin
                 push(b.off + (u - b.ulo) * b.stride(), ab.first, ab.second, K);
             }
         }
-        hdr[8 + k - step0] = cnt;
+        hdr[kHdrStepCounts + k - step0] = cnt;
     }
     int nstore = 0;
     {
@@ -328,14 +328,14 @@ void emit_tile(const Tree &tr, PlanWork &work, int root, int ta, int tb, int lin
             }
         }
     }
-    hdr[0] = first;
-    hdr[1] = nload;
-    hdr[2] = nstore;
-    hdr[3] = lds_steps;
-    hdr[4] = lds;
-    hdr[5] = static_cast<int>(pass->ops.size() / 4) - first;
-    hdr[6] = lin;
-    hdr[7] = tr.nodes[root].height;
+    hdr[kHdrFirst] = first;
+    hdr[kHdrLoads] = nload;
+    hdr[kHdrStores] = nstore;
+    hdr[kHdrSteps] = lds_steps;
+    hdr[kHdrLds] = lds;
+    hdr[kHdrEntries] = static_cast<int>(pass->ops.size() / 4) - first;
+    hdr[kHdrLevelIn] = lin;
+    hdr[kHdrHeight] = tr.nodes[root].height;
     hdr[kHdrLoadEnd] = load_end;
     hdr[kHdrSTile] = S;
     hdr[kHdrChunks] = K;

@@ -9,7 +9,16 @@
 namespace fht {
 
 constexpr int kHdrInts = 32;     // ints per tile-program header
-constexpr int kMaxSteps = 16;    // header slots 8 .. 23: entries of each merge step
+constexpr int kHdrFirst = 0;     // index of the program's first entry in its pass
+constexpr int kHdrLoads = 1;     // load entries
+constexpr int kHdrStores = 2;    // store entries
+constexpr int kHdrSteps = 3;     // merge steps run in LDS
+constexpr int kHdrLds = 4;       // LDS elements
+constexpr int kHdrEntries = 5;   // all entries
+constexpr int kHdrLevelIn = 6;   // level the pass starts from
+constexpr int kHdrHeight = 7;    // height of the pass root
+constexpr int kHdrStepCounts = 8;  // slots 8 .. 23: entries of each LDS merge step
+constexpr int kMaxSteps = 16;
 constexpr int kHdrLoadEnd = 24;  // first pass: largest end of a lane's padded load window
 constexpr int kHdrSTile = 25;    // positions per work item of this pass
 constexpr int kHdrChunks = 26;   // chunks K every entry of the program covers
