@@ -10,8 +10,9 @@ replayed from a captured HIP graph), and a ragged batch of 512 edge maps with
 sides log-uniform in [32, 2048] runs both ways.  Inputs are resident in HBM
 before timing starts.
 
-Prints one JSON line.  ``--gpus`` above 1 is rejected: this build runs on one
-GPU (images would be sharded across GPUs with no exchange).
+Prints one JSON line.  ``--gpus`` above 1 is rejected: the benchmark measures
+one GPU (several GPUs would each transform their own share of the images, with
+no exchange between them).
 """
 from __future__ import annotations
 
@@ -229,8 +230,9 @@ def _events(torch):
 def main():
     args = _parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); images would be sharded "
-              "across GPUs with no exchange, which this build does not do.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): several GPUs would each "
+              "transform their own share of the images, with no exchange, and that is not "
+              "implemented.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
