@@ -215,6 +215,7 @@ struct DevTables {
     int device = -1;
     const DevProgs *views[2] = {nullptr, nullptr};
     std::vector<int32_t *> items;               // per launch
+    bool adj_up = false;                         // adjoint tables uploaded (first adjoint call)
     int32_t *adj_offs[2] = {nullptr, nullptr};   // fused adjoint passes per lane view
     int32_t *adj_terms[2] = {nullptr, nullptr};
 };
@@ -341,7 +342,13 @@ struct fht_plan_s {
     size_t ws_off[4][2] = {};
     size_t ws_bytes = 0;
     std::vector<Launch> launches;    // in level order
-    fht::AdjointAxis adj[2];         // adjoint steps per lane view (float plans)
+    // Adjoint (float plans).  Its gather tables are built on first use (a
+    // forward-only caller never pays for them); the pass counts and the
+    // workspace layout are known at creation.
+    bool adj_view[2] = {false, false};  // lane views with an adjoint
+    int adj_npass[2] = {0, 0};          // fused gather passes per lane view
+    bool adj_built = false;          // guarded by mu
+    fht::AdjointAxis adj[2];         // adjoint steps per lane view
     std::vector<fht::AdjointPass> adjp[2];          // the steps fused into gather passes
     std::vector<size_t> adjp_offs[2], adjp_terms[2];  // where pass p starts in the tables
     size_t adj_ws_off[4][2] = {};
@@ -383,15 +390,6 @@ struct fht_plan_s {
             e = upload(launches[l].items, &ptr);
             t.items.push_back(ptr);
         }
-        for (int v = 0; e == hipSuccess && v < 2; ++v) {
-            std::vector<int32_t> offs, terms;
-            for (const fht::AdjointPass &ap : adjp[v]) {
-                offs.insert(offs.end(), ap.offs.begin(), ap.offs.end());
-                terms.insert(terms.end(), ap.terms.begin(), ap.terms.end());
-            }
-            e = upload(offs, &t.adj_offs[v]);
-            if (e == hipSuccess) e = upload(terms, &t.adj_terms[v]);
-        }
         if (e != hipSuccess) {
             free_tables(t);
             return hip_status(e);
@@ -402,6 +400,60 @@ struct fht_plan_s {
     }
 
     const fht::AxisPlan &ax(int v) const { return view[v]->plan; }
+
+    // The adjoint's host tables (caller holds mu).
+    void build_adjoint()
+    {
+        if (adj_built) return;
+        for (int v = 0; v < 2; ++v) {
+            if (!adj_view[v]) continue;
+            adj[v] = fht::plan_adjoint_axis(v == 0 ? R : C, static_cast<int>(split));
+            adjp[v] = fht::fuse_adjoint(adj[v], v == 0 ? C : R, kAdjointFuse);
+            size_t ob = 0, tb = 0;
+            for (const fht::AdjointPass &ap : adjp[v]) {
+                adjp_offs[v].push_back(ob);
+                adjp_terms[v].push_back(tb);
+                ob += ap.offs.size();
+                tb += ap.terms.size() / 2;
+            }
+        }
+        adj_built = true;
+    }
+
+    void adjoint_host()
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        build_adjoint();
+    }
+
+    // ... and their copy in `t` (device tables of the current device).
+    fht_status adjoint_tables(const DevTables *t)
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        build_adjoint();
+        DevTables &dt = const_cast<DevTables &>(*t);  // guarded by mu, like its creation
+        if (dt.adj_up) return FHT_OK;
+        hipError_t e = hipSuccess;
+        for (int v = 0; e == hipSuccess && v < 2; ++v) {
+            std::vector<int32_t> offs, terms;
+            for (const fht::AdjointPass &ap : adjp[v]) {
+                offs.insert(offs.end(), ap.offs.begin(), ap.offs.end());
+                terms.insert(terms.end(), ap.terms.begin(), ap.terms.end());
+            }
+            e = upload(offs, &dt.adj_offs[v]);
+            if (e == hipSuccess) e = upload(terms, &dt.adj_terms[v]);
+        }
+        if (e != hipSuccess) {
+            for (int v = 0; v < 2; ++v) {
+                if (dt.adj_offs[v]) (void)hipFree(dt.adj_offs[v]);
+                if (dt.adj_terms[v]) (void)hipFree(dt.adj_terms[v]);
+                dt.adj_offs[v] = dt.adj_terms[v] = nullptr;
+            }
+            return hip_status(e);
+        }
+        dt.adj_up = true;
+        return FHT_OK;
+    }
 
     bool narrow(int v, size_t p) const { return ax(v).passes[p].max_root_w <= kNarrowWidth; }
 
@@ -770,20 +822,15 @@ fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, fht_dtype 
         if (dtype != FHT_U8) {
             for (int v = 0; v < 2; ++v) {
                 if (!(quadrant_mask & (3u << (2 * v)))) continue;
-                p->adj[v] = fht::plan_adjoint_axis(v == 0 ? rows : cols, static_cast<int>(split));
-                p->adjp[v] = fht::fuse_adjoint(p->adj[v], v == 0 ? cols : rows, kAdjointFuse);
-                size_t ob = 0, tb = 0;
-                for (const fht::AdjointPass &ap : p->adjp[v]) {
-                    p->adjp_offs[v].push_back(ob);
-                    p->adjp_terms[v].push_back(tb);
-                    ob += ap.offs.size();
-                    tb += ap.terms.size() / 2;
-                }
+                // one gather pass per kAdjointFuse levels of the order tree
+                p->adj_view[v] = true;
+                const int levels = fht::make_tree_height(v == 0 ? rows : cols);
+                p->adj_npass[v] = (levels + kAdjointFuse - 1) / kAdjointFuse;
             }
             size_t aws = 0;
             for (int q = 0; q < 4; ++q) {
                 if (!(quadrant_mask & (1u << q))) continue;
-                const int npass = static_cast<int>(p->adjp[q >> 1].size());
+                const int npass = p->adj_npass[q >> 1];
                 const size_t wh = static_cast<size_t>(rows) * cols;
                 for (int b = 0; b < std::min(npass, 2); ++b) {
                     p->adj_ws_off[q][b] = aws;
@@ -1090,13 +1137,14 @@ int32_t fht_plan_adjoint_num_passes(fht_plan plan, int32_t v)
 {
     if (!plan || v < 0 || v > 1 || !(plan->qmask & (3u << (2 * v))) || plan->dtype == FHT_U8)
         return -1;
-    return static_cast<int32_t>(plan->adjp[v].size());
+    return plan->adj_npass[v];
 }
 
 fht_status fht_plan_adjoint_pass(fht_plan plan, int32_t v, int32_t pass, int32_t *levels,
                                  const int32_t **offs, const int32_t **terms, int32_t *n_terms)
 {
     if (fht_plan_adjoint_num_passes(plan, v) <= pass || pass < 0) return FHT_EINVAL;
+    plan->adjoint_host();
     const fht::AdjointPass &ap = plan->adjp[v][pass];
     if (levels) *levels = ap.levels;
     if (offs) *offs = ap.offs.data();
@@ -1110,6 +1158,7 @@ fht_status fht_plan_adjoint_tasks(fht_plan plan, int32_t v, const int32_t **task
 {
     if (!plan || v < 0 || v > 1 || !(plan->qmask & (3u << (2 * v)))) return FHT_EINVAL;
     if (plan->dtype == FHT_U8) return FHT_EDTYPE;
+    plan->adjoint_host();
     const fht::AdjointAxis &ax = plan->adj[v];
     if (tasks) *tasks = ax.tasks.data();
     if (levels) *levels = ax.levels;
@@ -1136,6 +1185,8 @@ fht_status fht_adjoint_many(fht_plan plan, int32_t n, const void *d_gouts, int64
     fht_status st = plan->tables(&t);
     if (st != FHT_OK) return st;
     if (injected_failure(&st)) return st;
+    st = plan->adjoint_tables(t);
+    if (st != FHT_OK) return st;
     const fht::Real real = plan->dtype == FHT_F64 ? fht::Real::F64 : fht::Real::F32;
     const size_t eb = acc_bytes(plan->dtype);
     const int64_t ws_stride = static_cast<int64_t>(align_up(plan->adj_ws_bytes, 256));
@@ -1145,7 +1196,7 @@ fht_status fht_adjoint_many(fht_plan plan, int32_t n, const void *d_gouts, int64
     int max_passes = 0;
     for (int q = 0; q < 4; ++q)
         if (plan->qmask & (1u << q))
-            max_passes = std::max(max_passes, static_cast<int>(plan->adjp[q >> 1].size()));
+            max_passes = std::max(max_passes, plan->adj_npass[q >> 1]);
     for (int k = 0; k < max_passes; ++k) {
         fht::AdjArgs a;
         std::memset(&a, 0, sizeof(a));
@@ -1156,7 +1207,7 @@ fht_status fht_adjoint_many(fht_plan plan, int32_t n, const void *d_gouts, int64
             if (!(plan->qmask & (1u << q))) continue;
             const int v = q >> 1;
             const fht::AdjointAxis &ax = plan->adj[v];
-            if (static_cast<int>(plan->adjp[v].size()) <= k) continue;
+            if (plan->adj_npass[v] <= k) continue;
             fht::AdjJob &j = a.job[nj++];
             j.src = k == 0 ? static_cast<const void *>(gout + plan->out_off[q] * eb)
                            : static_cast<const void *>(ws + plan->adj_ws_off[q][(k - 1) & 1]);
@@ -1179,7 +1230,7 @@ fht_status fht_adjoint_many(fht_plan plan, int32_t n, const void *d_gouts, int64
     c.dst_stride = gimg_stride;
     for (int q = 0; q < 4; ++q) {
         if (!(plan->qmask & (1u << q))) continue;
-        const int L = static_cast<int>(plan->adjp[q >> 1].size());
+        const int L = plan->adj_npass[q >> 1];
         // after the steps a negative-slope quadrant is in the mirrored frame
         c.src[q] = L > 0 ? static_cast<const void *>(ws + plan->adj_ws_off[q][(L - 1) & 1])
                          : static_cast<const void *>(gout + plan->out_off[q] * eb);

@@ -54,6 +54,8 @@ static int ceil_log2(int w)
     return h;
 }
 
+int make_tree_height(int W) { return ceil_log2(W); }
+
 Tree make_tree(int W, int split)
 {
     Tree tr;

@@ -53,6 +53,9 @@ struct Tree {
 
 Tree make_tree(int W, int split);
 
+// Height of the order tree of W lanes, ceil(log2 W), for either split.
+int make_tree_height(int W);
+
 // Row windows are tiled in 64-position chunks; a pass picks the largest
 // position tile whose widest window fits its target width.
 struct Schedule {
