@@ -147,6 +147,13 @@ const char *fht_plan_launch_kernel(fht_plan plan, int32_t launch);
  * before capturing fht_forward into a HIP graph.  Errors: FHT_ENODEV, FHT_ENOMEM,
  * FHT_EHIP. */
 fht_status fht_plan_upload(fht_plan plan);
+/* Copy only the plan's lane-view programs to the current HIP device
+ * (idempotent; programs are shared by every plan of the same lane count):
+ * what batches (fht_batch_create, fht_batch_upload) read, without the plan's
+ * own work items, which only fht_forward uses.  A server can call it on a
+ * planner thread so that its loop never waits for the copy.  Errors:
+ * FHT_EINVAL, FHT_ENODEV, FHT_ENOMEM, FHT_EHIP. */
+fht_status fht_plan_upload_programs(fht_plan plan);
 
 /*
  * Forward transform of one image (Alg. 1 for every selected quadrant).
@@ -220,6 +227,14 @@ fht_status fht_batch_prepare(fht_batch *out, const fht_plan *plans, int32_t n,
                              const void *const *d_imgs, void *const *d_outs);
 size_t fht_batch_tables_bytes(fht_batch batch);
 fht_status fht_batch_upload(fht_batch batch, void *d_tables, size_t bytes, void *stream);
+/* fht_batch_upload through caller-owned pinned host memory h_staging (at
+ * least fht_batch_tables_bytes bytes, from hipHostMalloc or a pinned
+ * allocator): the tables are written there and copied from there, so the copy
+ * is asynchronous (from pageable memory the runtime waits for it).  The caller
+ * keeps h_staging, like d_tables, alive until the copy has completed.  Errors:
+ * those of fht_batch_upload, and FHT_EINVAL for a null h_staging. */
+fht_status fht_batch_upload_staged(fht_batch batch, void *d_tables, size_t bytes,
+                                   void *h_staging, void *stream);
 
 /*
  * Adjoint (back-projection) of fht_forward for float32/float64 plans: the
@@ -291,7 +306,8 @@ fht_status fht_peaks(fht_plan plan, const void *d_out, int32_t k, int32_t radius
  * Fault injection for tests of error handling: the next `count` calls that
  * enqueue device work (fht_forward, fht_forward_many, fht_forward_launch,
  * fht_adjoint, fht_adjoint_many, fht_peaks,
- * fht_batch_upload, fht_batch_run, fht_batch_run_launch) return `code` after checking their
+ * fht_batch_upload, fht_batch_upload_staged, fht_batch_run, fht_batch_run_launch) return
+ * `code` after checking their
  * arguments and before enqueuing anything.  count <= 0 or code == FHT_OK
  * disarms it.  Process-wide; safe to call from any thread.
  */

@@ -38,7 +38,8 @@ __all__ = [
     "HoughFunction", "hough_autograd", "fht_peaks_workspace_bytes", "fht_peaks", "PEAK_DTYPE",
     "fht_plan_work", "fht_plan_launch_kernel", "fht_plan_workspace_bytes_many",
     "fht_forward_many", "fht_plan_adjoint_workspace_bytes_many", "fht_adjoint_many",
-    "fht_plan_adjoint_num_passes", "fht_plan_adjoint_pass",
+    "fht_plan_adjoint_num_passes", "fht_plan_adjoint_pass", "fht_batch_upload_staged",
+    "fht_plan_upload_programs",
 ]
 
 FHT_U8, FHT_F32, FHT_F64 = 0, 1, 2
@@ -60,6 +61,7 @@ EXPORTED = (
     "fht_peaks_workspace_bytes", "fht_peaks", "fht_plan_work", "fht_plan_launch_kernel",
     "fht_plan_workspace_bytes_many", "fht_forward_many", "fht_plan_adjoint_workspace_bytes_many",
     "fht_adjoint_many", "fht_plan_adjoint_num_passes", "fht_plan_adjoint_pass",
+    "fht_batch_upload_staged", "fht_plan_upload_programs",
 )
 
 # struct fht_peak
@@ -118,6 +120,8 @@ _sig("fht_batch_prepare", _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i32,
 _sig("fht_batch_tables_bytes", _sz, _vp)
 _sig("fht_batch_upload", _i32, _vp, _vp, _sz, _vp)
 _sig("fht_debug_fail_next", None, _i32, _i32)
+_sig("fht_batch_upload_staged", _i32, _vp, _vp, _sz, _vp, _vp)
+_sig("fht_plan_upload_programs", _i32, _vp)
 _sig("fht_plan_adjoint_workspace_bytes", _sz, _vp)
 _sig("fht_plan_adjoint_tasks", _i32, _vp, _i32, _ppi32, _pi32, _pi32)
 _sig("fht_adjoint", _i32, _vp, _vp, _vp, _vp, _vp)
@@ -202,6 +206,10 @@ def fht_plan_upload(plan: int) -> None:
     _check(_lib.fht_plan_upload(plan), "fht_plan_upload")
 
 
+def fht_plan_upload_programs(plan: int) -> None:
+    _check(_lib.fht_plan_upload_programs(plan), "fht_plan_upload_programs")
+
+
 def fht_forward(plan: int, d_img: int, d_out: int, d_ws: int | None, stream: int | None) -> None:
     _check(_lib.fht_forward(plan, d_img, d_out, d_ws, stream), "fht_forward")
 
@@ -255,6 +263,12 @@ def fht_batch_tables_bytes(batch: int) -> int:
 
 def fht_batch_upload(batch: int, d_tables: int, nbytes: int, stream: int | None) -> None:
     _check(_lib.fht_batch_upload(batch, d_tables, nbytes, stream), "fht_batch_upload")
+
+
+def fht_batch_upload_staged(batch: int, d_tables: int, nbytes: int, h_staging: int,
+                            stream: int | None) -> None:
+    _check(_lib.fht_batch_upload_staged(batch, d_tables, nbytes, h_staging, stream),
+           "fht_batch_upload_staged")
 
 
 def fht_debug_fail_next(code: int, count: int = 1) -> None:
@@ -592,12 +606,21 @@ class Batch:
         self.tables_bytes = fht_batch_tables_bytes(self.handle)
         self.tables = None
 
-    def upload(self, tables, stream=None) -> None:
+    def upload(self, tables, stream=None, staging=None) -> None:
         """Enqueue the copy of the device tables into `tables` (a device tensor
-        of at least ``tables_bytes`` bytes, kept alive with the batch)."""
+        of at least ``tables_bytes`` bytes, kept alive with the batch); with
+        `staging` (a pinned host tensor as large) the copy goes through it and
+        does not wait for the stream."""
         if tables.numel() * tables.element_size() < self.tables_bytes:
             raise ValueError("table buffer too small")
-        fht_batch_upload(self.handle, tables.data_ptr(), self.tables_bytes, _stream_handle(stream))
+        if staging is None:
+            fht_batch_upload(self.handle, tables.data_ptr(), self.tables_bytes, _stream_handle(stream))
+        else:
+            if staging.numel() * staging.element_size() < self.tables_bytes or not staging.is_pinned():
+                raise ValueError("staging buffer too small or not pinned")
+            fht_batch_upload_staged(self.handle, tables.data_ptr(), self.tables_bytes,
+                                    staging.data_ptr(), _stream_handle(stream))
+            self.staging = staging
         self.tables = tables
 
     def __del__(self):

@@ -129,7 +129,7 @@ std::string kernel_name(Combo c, int threads, bool table)
 // Device copy of one lane view's tile programs.
 struct DevProgs {
     int device = -1;
-    int32_t *hdrs = nullptr;
+    int32_t *hdrs = nullptr;  // inside the allocation of ops, after the entries
     int4 *ops = nullptr;
 };
 
@@ -149,8 +149,7 @@ struct ViewProgs {
             int cur = 0;
             const bool have = hipGetDevice(&cur) == hipSuccess;
             (void)hipSetDevice(d.device);
-            if (d.hdrs) (void)hipFree(d.hdrs);
-            if (d.ops) (void)hipFree(d.ops);
+            if (d.ops) (void)hipFree(d.ops);  // headers share the allocation
             if (have) (void)hipSetDevice(cur);
         }
     }
@@ -180,15 +179,17 @@ struct ViewProgs {
         ops.resize(ops.size() + 4 * fht::kEntryPrefetch, 0);
         DevProgs x;
         x.device = d;
+        // headers and entries in one allocation (entries first: 16-byte aligned)
+        const size_t n_ops = ops.size();
+        ops.insert(ops.end(), hdrs.begin(), hdrs.end());
         int32_t *o = nullptr;
-        e = upload(hdrs, &x.hdrs);
-        if (e == hipSuccess) e = upload(ops, &o);
-        x.ops = reinterpret_cast<int4 *>(o);
+        e = upload(ops, &o);
         if (e != hipSuccess) {
-            if (x.hdrs) (void)hipFree(x.hdrs);
             if (o) (void)hipFree(o);
             return hip_status(e);
         }
+        x.ops = reinterpret_cast<int4 *>(o);
+        x.hdrs = o + n_ops;
         dev.push_back(x);
         *out = &dev.back();
         return FHT_OK;
@@ -214,7 +215,8 @@ struct ViewProgs {
 struct DevTables {
     int device = -1;
     const DevProgs *views[2] = {nullptr, nullptr};
-    std::vector<int32_t *> items;               // per launch
+    int32_t *items_blob = nullptr;              // every launch's items, one allocation
+    std::vector<int32_t *> items;               // per launch, into items_blob
     bool adj_up = false;                         // adjoint tables uploaded (first adjoint call)
     int32_t *adj_offs[2] = {nullptr, nullptr};   // fused adjoint passes per lane view
     int32_t *adj_terms[2] = {nullptr, nullptr};
@@ -226,8 +228,7 @@ void free_tables(DevTables &t)
         if (p) (void)hipFree(p);
     for (int32_t *p : t.adj_terms)
         if (p) (void)hipFree(p);
-    for (int32_t *p : t.items)
-        if (p) (void)hipFree(p);
+    if (t.items_blob) (void)hipFree(t.items_blob);
     t = DevTables{};
 }
 
@@ -385,10 +386,17 @@ struct fht_plan_s {
             const fht_status st = view[v]->device_progs(&t.views[v]);
             if (st != FHT_OK) return st;
         }
-        for (size_t l = 0; e == hipSuccess && l < launches.size(); ++l) {
-            int32_t *ptr = nullptr;
-            e = upload(launches[l].items, &ptr);
-            t.items.push_back(ptr);
+        {
+            // one allocation and one copy for all launches (fewer runtime calls)
+            std::vector<int32_t> all;
+            std::vector<size_t> at;
+            for (const Launch &L : launches) {
+                at.push_back(all.size());
+                all.insert(all.end(), L.items.begin(), L.items.end());
+            }
+            e = upload(all, &t.items_blob);
+            for (size_t l = 0; l < launches.size(); ++l)
+                t.items.push_back(t.items_blob ? t.items_blob + at[l] : nullptr);
         }
         if (e != hipSuccess) {
             free_tables(t);
@@ -960,6 +968,20 @@ fht_status fht_plan_upload(fht_plan plan)
     return plan->tables(&t);
 }
 
+fht_status fht_plan_upload_programs(fht_plan plan)
+{
+    if (!plan) return FHT_EINVAL;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0) return FHT_ENODEV;
+    for (int v = 0; v < 2; ++v) {
+        if (!plan->view[v]) continue;
+        const DevProgs *p = nullptr;
+        const fht_status st = plan->view[v]->device_progs(&p);
+        if (st != FHT_OK) return st;
+    }
+    return FHT_OK;
+}
+
 fht_status fht_forward(fht_plan plan, const void *d_img, void *d_out, void *d_ws, void *stream)
 {
     const DevTables *t = nullptr;
@@ -1031,6 +1053,25 @@ fht_status fht_batch_upload(fht_batch batch, void *d_tables, size_t bytes, void 
     st = finish_jobs(batch);
     if (st != FHT_OK) return st;
     e = hipMemcpyAsync(d_tables, batch->blob.data(), batch->blob.size(), hipMemcpyHostToDevice,
+                       static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_status(e);
+    batch->dev = static_cast<char *>(d_tables);
+    return FHT_OK;
+}
+
+fht_status fht_batch_upload_staged(fht_batch batch, void *d_tables, size_t bytes, void *h_staging,
+                                   void *stream)
+{
+    if (!batch || !d_tables || !h_staging || bytes < batch->blob.size() || batch->owns)
+        return FHT_EINVAL;
+    fht_status st = FHT_OK;
+    if (injected_failure(&st)) return st;
+    hipError_t e = hipGetDevice(&batch->device);
+    if (e != hipSuccess) return hip_status(e);
+    st = finish_jobs(batch);
+    if (st != FHT_OK) return st;
+    std::memcpy(h_staging, batch->blob.data(), batch->blob.size());
+    e = hipMemcpyAsync(d_tables, h_staging, batch->blob.size(), hipMemcpyHostToDevice,
                        static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_status(e);
     batch->dev = static_cast<char *>(d_tables);

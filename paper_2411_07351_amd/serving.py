@@ -105,15 +105,26 @@ def footprint(plan, kind: str) -> int:
 
 
 class PlanCache:
-    """Plans made on host threads, cached (LRU) by shape, dtype and split."""
+    """Plans made on host threads, cached (LRU) by shape, dtype and split.
+    `prepare(plan)`, if given, runs on the planner thread after planning (the
+    GPU executor copies the plan's tables to the device there, so that the
+    serving loop never waits for it)."""
 
-    def __init__(self, threads: int = 8, capacity: int = 256, schedule: dict | None = None):
+    def __init__(self, threads: int = 8, capacity: int = 256, schedule: dict | None = None,
+                 prepare=None):
         self._pool = ThreadPoolExecutor(max_workers=max(1, threads),
                                         thread_name_prefix="fht-plan")
         self._lru: OrderedDict = OrderedDict()
         self._lock = threading.Lock()
         self._capacity = capacity
         self._schedule = schedule
+        self._prepare = prepare
+
+    def _make(self, rows: int, cols: int, kind: str, split: str):
+        plan = B.Plan(rows, cols, kind, split, schedule=self._schedule)
+        if self._prepare is not None:
+            self._prepare(plan)
+        return plan
 
     def get(self, rows: int, cols: int, kind: str, split: str) -> Future:
         key = (rows, cols, kind, split)
@@ -122,7 +133,7 @@ class PlanCache:
             if fut is not None:
                 self._lru.move_to_end(key)
                 return fut
-            fut = self._pool.submit(B.Plan, rows, cols, kind, split, schedule=self._schedule)
+            fut = self._pool.submit(self._make, rows, cols, kind, split)
             self._lru[key] = fut
             while len(self._lru) > self._capacity:
                 self._lru.popitem(last=False)
@@ -174,6 +185,12 @@ class GpuExecutor:
     def n_streams(self) -> int:
         return len(self.streams)
 
+    def prepare(self, plan) -> None:
+        """Copy a plan's lane-view programs (what batches read) to the device,
+        on a planner thread."""
+        with self.torch.cuda.device(self.device):
+            B.fht_plan_upload_programs(plan.handle)
+
     def launch(self, reqs: Sequence[Request], slot: int) -> dict:
         torch = self.torch
         stream = self.streams[slot]
@@ -192,9 +209,13 @@ class GpuExecutor:
             batch = B.Batch([r.plan for r in reqs], imgs, outs, defer_upload=True)
             ws = torch.empty(max(batch.ws_bytes, 1), dtype=torch.uint8, device=self.device)
             tables = torch.empty(batch.tables_bytes, dtype=torch.uint8, device=self.device)
-            h = {"batch": batch, "imgs": imgs, "outs": outs, "ws": ws, "tables": tables}
+            # pinned staging: the table copy is asynchronous, so the loop never
+            # waits here for the batches already on the stream
+            staging = torch.empty(batch.tables_bytes, dtype=torch.uint8, pin_memory=True)
+            h = {"batch": batch, "imgs": imgs, "outs": outs, "ws": ws, "tables": tables,
+                 "staging": staging}
             try:
-                batch.upload(tables, stream)
+                batch.upload(tables, stream, staging)
                 batch.run(ws, stream)
             except B.FhtError:
                 # keep what may already be enqueued alive until the stream passes it
@@ -245,7 +266,8 @@ class Server:
         self.depth = max(1, int(depth))
         self.clock = clock or WallClock()
         self.keep_outputs = keep_outputs
-        self.plans = PlanCache(plan_threads, plan_cache, schedule)
+        self.plans = PlanCache(plan_threads, plan_cache, schedule,
+                               getattr(executor, "prepare", None))
         self.in_use = 0
         self.peak_in_use = 0
         self.peak_running = 0

@@ -57,5 +57,8 @@ def test_null_arguments_are_rejected():
     lib.fht_batch_run.restype = ctypes.c_int32
     lib.fht_batch_run.argtypes = [ctypes.c_void_p] * 3
     assert lib.fht_batch_run(None, None, None) == -1
+    lib.fht_plan_upload_programs.restype = ctypes.c_int32
+    lib.fht_plan_upload_programs.argtypes = [ctypes.c_void_p]
+    assert lib.fht_plan_upload_programs(None) == -1
     F.fht_plan_destroy(None)
     F.fht_batch_destroy(None)

@@ -215,6 +215,9 @@ def test_fault_hook_of_the_c_abi():
         with pytest.raises(F.FhtError) as e:
             F.fht_batch_upload(b, fake, 1, None)  # too small: argument check first
         assert e.value.status == -1
+        with pytest.raises(F.FhtError) as e:  # the staged form needs its host buffer
+            F.fht_batch_upload_staged(b, fake, F.fht_batch_tables_bytes(b), 0, None)
+        assert e.value.status == -1
     finally:
         F.fht_debug_fail_next(0, 0)
         F.fht_batch_destroy(b)
