@@ -323,7 +323,9 @@ void fht_debug_fail_next(fht_status code, int32_t count);
  *         [7] height of the pass root, [8 + k] entries of LDS merge step k,
  *         [24] first pass: end of the padded load windows, [25] positions per item,
  *         [26] chunks k of every entry, [27] 1 if the stores add (the root's
- *         last merge), [28] load-merges, [29] LDS element bytes
+ *         last merge), [28] load-merges, [29] LDS element bytes, [30] lane base:
+ *         added to every src and dst row the program's entries name (programs
+ *         of pass roots of equal widths share entries)
  *   ops   4 ints each, every entry covering k whole 64-position chunks, in the
  *         order loads, load-merges, merge steps, stores:
  *         load  {lds, src row, position offset, k}: lds[d+c] = src[row][(s0+off+c) mod H]

@@ -447,6 +447,17 @@ __device__ __forceinline__ void run_item(TL *lds, cptr<int32_t> hdr, const int4 
     const int lane = threadIdx.x & 63;
     const int nload = hdr[kHdrLoads], nstore = hdr[kHdrStores], nsteps = hdr[kHdrSteps];
     const int H = job.H;
+    constexpr bool PAIR_OUT = PAIR && sizeof(TD) == 4 && std::is_signed<TD>::value;
+
+    // Programs of pass roots of equal widths share their entries; the lane
+    // base moves the rows they name to this program's root.
+    {
+        const int64_t lb = hdr[kHdrLaneBase];
+        const int64_t src_row = FROM_IMAGE ? ((job.flags & JF_COLS) ? 1 : job.ld) : H;
+        src += lb * src_row * static_cast<int64_t>(sizeof(TSrc));
+        dst += lb * H * static_cast<int64_t>(sizeof(TD));
+        if constexpr (PAIR_OUT) dst2 += lb * H * static_cast<int64_t>(sizeof(TD));
+    }
 
     // load-merge entries: the planner emits them only for LDS elements of
     // other than 4 bytes (4-byte rows are loaded straight into LDS instead)
@@ -485,7 +496,6 @@ __device__ __forceinline__ void run_item(TL *lds, cptr<int32_t> hdr, const int4 
     }
     __syncthreads();
 
-    constexpr bool PAIR_OUT = PAIR && sizeof(TD) == 4 && std::is_signed<TD>::value;
     const bool unmirror = (job.flags & JF_FINAL) && (PAIR_OUT || (job.flags & JF_MIRROR));
     if (hdr[kHdrStoreMerge])  // the stores add the root's last merge
         store_rows<K, NW, TL, TD, PAIR_OUT, true>(lds, step_ent, nstore, reinterpret_cast<TD *>(dst),
@@ -540,7 +550,6 @@ __global__ void __launch_bounds__(NT) fht_pass_kernel(PassArgs args, int n_items
         dst += od;
         dst2 += od;
     }
-
     switch (hdr[kHdrChunks]) {
     case 1: run_item<NT, 1, TSrc, TL, TD, FROM_IMAGE, PAIR>(lds, hdr, ent, pre, job, src, dst, dst2, item.z); break;
     case 2: run_item<NT, 2, TSrc, TL, TD, FROM_IMAGE, PAIR>(lds, hdr, ent, pre, job, src, dst, dst2, item.z); break;

@@ -24,7 +24,14 @@
 // runs whole chunks: the positions past a window are computed but never
 // read back.  A right child carries the few positions of slack that the
 // shifted whole-chunk reads of its last row need, so they stay inside it.
+//
+// A node's subtree depends on its width alone, so the pass roots of equal
+// widths (a handful per pass) run the same programs on different lanes: each
+// width is planned once, and the other roots' headers point at its entries
+// with a lane base that the kernels add to every row.
 #include "plan.hpp"
+
+#include <array>
 
 #include <algorithm>
 #include <map>
@@ -349,6 +356,21 @@ void emit_tile(const Tree &tr, PlanWork &work, int root, int ta, int tb, int lin
     if (widest > K * kChunk || K > kMaxChunks) pass->fits = false;
 }
 
+// Appends a header for program `src` of the pass moved by `delta` lanes: the
+// program of a root with the same width as the root of `src`.  A node's
+// subtree, and so every slope table, block and LDS offset of its tiles,
+// depends on its width only; lanes enter the entries only as the source rows
+// of loads and load-merges and the destination rows of stores, which the
+// kernels offset by the header's lane base.  The two headers share entries.
+void share_tile(Pass *pass, int src, int delta)
+{
+    const int32_t *sh = pass->hdrs.data() + static_cast<size_t>(src) * kHdrInts;
+    int32_t hdr[kHdrInts];
+    std::copy(sh, sh + kHdrInts, hdr);
+    hdr[kHdrLaneBase] += delta;
+    pass->hdrs.insert(pass->hdrs.end(), hdr, hdr + kHdrInts);
+}
+
 void build_pass(const Tree &tr, PlanWork &work, int lin, int lout, int T, int S, int K,
                 int pad, int H, bool load_merge, Pass *pass)
 {
@@ -358,13 +380,21 @@ void build_pass(const Tree &tr, PlanWork &work, int lin, int lout, int T, int S,
     pass->S = S;
     std::vector<int> roots;
     collect_frontier(tr, 0, lout, &roots);
+    // first root of each width: {width, its lane offset, its first program}
+    std::vector<std::array<int, 3>> made;
     for (int r : roots) {
         const int w = tr.nodes[r].w;
         pass->max_root_w = std::max(pass->max_root_w, w);
         const int tt = (T <= 0) ? w : T;
-        for (int ta = 0; ta < w; ta += tt) {
+        const std::array<int, 3> *same = nullptr;
+        for (const auto &m : made)
+            if (m[0] == w) same = &m;
+        const int prog0 = static_cast<int>(pass->hdrs.size() / kHdrInts);
+        const std::array<int, 3> here{w, tr.nodes[r].a, prog0};
+        for (int ta = 0, j = 0; ta < w; ta += tt, ++j) {
             const int prog = static_cast<int>(pass->hdrs.size() / kHdrInts);
-            emit_tile(tr, work, r, ta, std::min(w, ta + tt), lin, S, K, pad, load_merge, pass);
+            if (same) share_tile(pass, (*same)[2] + j, here[1] - (*same)[1]);
+            else emit_tile(tr, work, r, ta, std::min(w, ta + tt), lin, S, K, pad, load_merge, pass);
             for (int s0 = 0; s0 < H; s0 += S) {
                 pass->items.push_back(prog);
                 pass->items.push_back(0);
@@ -372,6 +402,7 @@ void build_pass(const Tree &tr, PlanWork &work, int lin, int lout, int T, int S,
                 pass->items.push_back(0);
             }
         }
+        if (!same) made.push_back(here);
     }
 }
 
@@ -386,8 +417,11 @@ void build_pass_fitted(const Tree &tr, PlanWork &work, int lin, int lout, int T,
     std::vector<int> roots;
     collect_frontier(tr, 0, lout, &roots);
     int widest = 0;
+    std::vector<int> seen;  // root widths probed (equal widths, equal windows)
     for (int r : roots) {
         const int w = tr.nodes[r].w;
+        if (std::find(seen.begin(), seen.end(), w) != seen.end()) continue;
+        seen.push_back(w);
         const int tt = (T <= 0) ? w : T;
         for (int ta = 0; ta < w; ta += tt) {
             work.blocks.clear();

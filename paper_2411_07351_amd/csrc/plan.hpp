@@ -25,6 +25,7 @@ constexpr int kHdrChunks = 26;   // chunks K every entry of the program covers
 constexpr int kHdrStoreMerge = 27;  // 1: the stores add the root's last merge (see emit_tile)
 constexpr int kHdrLoadMerges = 28;  // load-merge entries (step 1 read from the source rows)
 constexpr int kHdrElemBytes = 29;   // LDS element bytes of the pass
+constexpr int kHdrLaneBase = 30;    // lanes added to every row the entries name (see share_tile)
 constexpr int kChunk = 64;       // positions per chunk (one wavefront access)
 constexpr int kMaxFirstLevels = 6;  // first-pass roots have at most 64 lanes
 constexpr int kMaxTarget = 256;     // widest row window a schedule may ask for

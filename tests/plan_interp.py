@@ -9,7 +9,9 @@ them and checks the invariants the kernel relies on:
   rows) ``lds[d + c] = src[a][(s0 + off + c) mod H] + src[b][(s0 + off + r +
   c) mod H]`` with ``off | r << 16`` in the entry's last field; store ``dst[row][s0 + c] = lds[d + c]`` (``+ lds[b + c]``
   when the header says the stores add the root's last merge) for
-  ``c < min(64 k, limit)`` and ``s0 + c < H``;
+  ``c < min(64 k, limit)`` and ``s0 + c < H``; every row an entry names is
+  moved by the header's lane base (programs of equal-width roots share
+  entries);
 * every LDS access stays inside the program's footprint;
 * no merge step reads a range another entry of the same step writes;
 * every stored value was computed from loaded data only (positions a window
@@ -44,12 +46,16 @@ def run_plan_tables(plan_handle, img, q, check=True):
             hdr = tb["hdrs"][prog]
             first, nload, nstore, nsteps, lds_n, nops = (int(x) for x in hdr[:6])
             K, store_merge, nlm = int(hdr[26]), bool(hdr[27]), int(hdr[28])
+            base = int(hdr[30])  # lanes added to every row the entries name
             if check:
                 # programs with merges fold the last one into the stores
                 assert store_merge == (int(hdr[7]) > int(hdr[6]))
             assert nops == nload + nlm + nstore + sum(int(c) for c in hdr[8:8 + nsteps])
             assert int(hdr[25]) == tb["s_tile"]
-            ops = tb["ops"][first:first + nops]
+            ops = tb["ops"][first:first + nops].astype(np.int64)
+            ops[:nload + nlm, 1] += base
+            ops[nload:nload + nlm, 2] += base
+            ops[nops - nstore:, 1] += base
             lds = np.zeros(lds_n, dtype=src.dtype)
             valid = np.zeros(lds_n, dtype=bool)
             if check and int(hdr[6]) == 0:
