@@ -64,6 +64,7 @@ typedef enum { FHT_SPLIT_S = 0, FHT_SPLIT_T = 1 } fht_split;
 
 typedef struct fht_plan_s *fht_plan;
 typedef struct fht_batch_s *fht_batch;
+typedef struct fht_planner_s *fht_planner;
 
 /*
  * Tiling of the fused passes (not in the paper: the paper's recursion runs one
@@ -154,6 +155,44 @@ fht_status fht_plan_upload(fht_plan plan);
  * planner thread so that its loop never waits for the copy.  Errors:
  * FHT_EINVAL, FHT_ENODEV, FHT_ENOMEM, FHT_EHIP. */
 fht_status fht_plan_upload_programs(fht_plan plan);
+/* The same for n plans at once: the programs of all their lane views not yet
+ * on the current device go in one device allocation and one copy, through
+ * two 4 MiB pinned staging buffers and a non-blocking stream of the library
+ * (so the copy never waits for work on other streams).  The block is freed
+ * with the last view in it.  Errors: FHT_EINVAL (n < 0, or a null plan),
+ * FHT_ENODEV, FHT_ENOMEM, FHT_EHIP; on an error no view is marked as copied. */
+fht_status fht_plan_upload_programs_many(const fht_plan *plans, int32_t n);
+
+/*
+ * Planner pool: plans (fht_plan_create) made on `threads` worker threads of
+ * the library, and, for device >= 0, their lane-view programs copied to that
+ * HIP device by one more thread of the pool, up to 32 finished plans per
+ * fht_plan_upload_programs_many (small copies from many threads serialise
+ * inside the HIP runtime).  A request loop only submits and polls: it never
+ * runs the planner, holds no lock of its own language's runtime while plans
+ * are made, and never waits for the copies.  device -1 plans on the host only.
+ *   fht_planner_create  threads in [1, 256].  Errors: FHT_EINVAL, FHT_ENOMEM.
+ *   fht_planner_submit  queues one plan (arguments as fht_plan_create; the
+ *                       schedule, if any, is copied) and returns its ticket
+ *                       (0, 1, 2, ... in submission order).  Errors: FHT_EINVAL,
+ *                       FHT_ENOMEM.  Bad plan arguments are reported by the poll.
+ *   fht_planner_poll    1 once the ticket's plan is finished: *status is what
+ *                       making (and copying) it returned and *plan the plan,
+ *                       owned by the caller from then on (NULL unless *status
+ *                       is FHT_OK); the ticket is then forgotten.  0 while it
+ *                       is queued or being made, -1 for a null argument or a
+ *                       ticket never issued or already taken.
+ *   fht_planner_destroy drops queued plans, waits for those being made, frees
+ *                       finished plans no poll took, and joins the threads;
+ *                       NULL is ignored.
+ * Submit and poll may be called from any threads.
+ */
+fht_status fht_planner_create(int32_t threads, int32_t device, fht_planner *out);
+fht_status fht_planner_submit(fht_planner planner, int32_t rows, int32_t cols, fht_dtype dtype,
+                              fht_split split, uint32_t quadrant_mask, const fht_schedule *sched,
+                              int64_t *ticket);
+int32_t fht_planner_poll(fht_planner planner, int64_t ticket, fht_plan *plan, fht_status *status);
+void fht_planner_destroy(fht_planner planner);
 
 /*
  * Forward transform of one image (Alg. 1 for every selected quadrant).

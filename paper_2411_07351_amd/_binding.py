@@ -39,7 +39,8 @@ __all__ = [
     "fht_plan_work", "fht_plan_launch_kernel", "fht_plan_workspace_bytes_many",
     "fht_forward_many", "fht_plan_adjoint_workspace_bytes_many", "fht_adjoint_many",
     "fht_plan_adjoint_num_passes", "fht_plan_adjoint_pass", "fht_batch_upload_staged",
-    "fht_plan_upload_programs",
+    "fht_plan_upload_programs", "fht_planner_create", "fht_planner_submit", "fht_planner_poll",
+    "fht_planner_destroy", "fht_plan_upload_programs_many", "STATUS",
 ]
 
 FHT_U8, FHT_F32, FHT_F64 = 0, 1, 2
@@ -62,6 +63,8 @@ EXPORTED = (
     "fht_plan_workspace_bytes_many", "fht_forward_many", "fht_plan_adjoint_workspace_bytes_many",
     "fht_adjoint_many", "fht_plan_adjoint_num_passes", "fht_plan_adjoint_pass",
     "fht_batch_upload_staged", "fht_plan_upload_programs",
+    "fht_planner_create", "fht_planner_submit", "fht_planner_poll", "fht_planner_destroy",
+    "fht_plan_upload_programs_many",
 )
 
 # struct fht_peak
@@ -122,6 +125,12 @@ _sig("fht_batch_upload", _i32, _vp, _vp, _sz, _vp)
 _sig("fht_debug_fail_next", None, _i32, _i32)
 _sig("fht_batch_upload_staged", _i32, _vp, _vp, _sz, _vp, _vp)
 _sig("fht_plan_upload_programs", _i32, _vp)
+_sig("fht_plan_upload_programs_many", _i32, ctypes.POINTER(_vp), _i32)
+_sig("fht_planner_create", _i32, _i32, _i32, ctypes.POINTER(_vp))
+_sig("fht_planner_submit", _i32, _vp, _i32, _i32, _i32, _i32, _u32, ctypes.POINTER(fht_schedule),
+     ctypes.POINTER(_i64))
+_sig("fht_planner_poll", _i32, _vp, _i64, ctypes.POINTER(_vp), ctypes.POINTER(_i32))
+_sig("fht_planner_destroy", None, _vp)
 _sig("fht_plan_adjoint_workspace_bytes", _sz, _vp)
 _sig("fht_plan_adjoint_tasks", _i32, _vp, _i32, _ppi32, _pi32, _pi32)
 _sig("fht_adjoint", _i32, _vp, _vp, _vp, _vp, _vp)
@@ -208,6 +217,38 @@ def fht_plan_upload(plan: int) -> None:
 
 def fht_plan_upload_programs(plan: int) -> None:
     _check(_lib.fht_plan_upload_programs(plan), "fht_plan_upload_programs")
+
+
+def fht_plan_upload_programs_many(plans) -> None:
+    arr = (_vp * len(plans))(*plans)
+    _check(_lib.fht_plan_upload_programs_many(arr, len(plans)), "fht_plan_upload_programs_many")
+
+
+def fht_planner_create(threads: int, device: int = -1) -> int:
+    h = _vp()
+    _check(_lib.fht_planner_create(threads, device, ctypes.byref(h)), "fht_planner_create")
+    return h.value
+
+
+def fht_planner_submit(planner: int, rows: int, cols: int, dtype: int, split: int,
+                       quadrant_mask: int = 15, schedule: fht_schedule | None = None) -> int:
+    t = _i64()
+    sched = ctypes.byref(schedule) if schedule is not None else None
+    _check(_lib.fht_planner_submit(planner, rows, cols, dtype, split, quadrant_mask, sched,
+                                   ctypes.byref(t)), "fht_planner_submit")
+    return t.value
+
+
+def fht_planner_poll(planner: int, ticket: int) -> tuple:
+    """(state, plan handle or None, status): state 1 finished (the caller owns
+    the plan), 0 pending, -1 unknown ticket."""
+    h, st = _vp(), _i32()
+    r = _lib.fht_planner_poll(planner, ticket, ctypes.byref(h), ctypes.byref(st))
+    return r, h.value, st.value
+
+
+def fht_planner_destroy(planner: int) -> None:
+    _lib.fht_planner_destroy(planner)
 
 
 def fht_forward(plan: int, d_img: int, d_out: int, d_ws: int | None, stream: int | None) -> None:
@@ -399,7 +440,6 @@ class Plan:
 
     def __init__(self, rows: int, cols: int, dtype="u8", split="S", quadrants=(0, 1, 2, 3),
                  schedule: dict | None = None):
-        torch = _torch()
         self.rows, self.cols = int(rows), int(cols)
         self.dtype_code = _dtype_code(dtype)
         self.split = _split_code(split)
@@ -408,7 +448,24 @@ class Plan:
         for q in self.quadrants:
             mask |= 1 << q
         sched = fht_schedule(**schedule) if schedule else None
-        self.handle = fht_plan_create(self.rows, self.cols, self.dtype_code, self.split, mask, sched)
+        self._setup(fht_plan_create(self.rows, self.cols, self.dtype_code, self.split, mask, sched))
+
+    @classmethod
+    def adopt(cls, handle: int, rows: int, cols: int, dtype="u8", split="S",
+              quadrants=(0, 1, 2, 3)) -> "Plan":
+        """Wraps (and takes ownership of) a plan made by the C library with
+        these arguments, e.g. by fht_planner."""
+        self = cls.__new__(cls)
+        self.rows, self.cols = int(rows), int(cols)
+        self.dtype_code = _dtype_code(dtype)
+        self.split = _split_code(split)
+        self.quadrants = tuple(sorted(set(int(q) for q in quadrants)))
+        self._setup(handle)
+        return self
+
+    def _setup(self, handle: int) -> None:
+        torch = _torch()
+        self.handle = handle
         self.in_dtype = (torch.uint8, torch.float32, torch.float64)[self.dtype_code]
         self.out_dtype = (torch.int32, torch.float32, torch.float64)[self.dtype_code]
         self.out_elems = fht_plan_out_elems(self.handle)

@@ -39,7 +39,7 @@ def _torch_lib_dir() -> str | None:
     return None
 
 
-SOURCES = [("plan.cpp", "cxx"), ("kernels.hip", "hip"), ("adjoint.hip", "hip"), ("peaks.hip", "hip"), ("api.hip", "hip")]
+SOURCES = [("plan.cpp", "cxx"), ("kernels.hip", "hip"), ("adjoint.hip", "hip"), ("peaks.hip", "hip"), ("api.hip", "hip"), ("planner.hip", "hip")]
 
 
 def _run(cmd):

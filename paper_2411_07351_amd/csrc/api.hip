@@ -126,11 +126,119 @@ std::string kernel_name(Combo c, int threads, bool table)
            (pair ? "true" : "false") + ">";
 }
 
+// Device memory freed (on its own device) with the last view using it.
+std::shared_ptr<void> device_block(void *p, int device)
+{
+    return std::shared_ptr<void>(p, [device](void *q) {
+        int cur = 0;
+        const bool have = hipGetDevice(&cur) == hipSuccess;
+        (void)hipSetDevice(device);
+        (void)hipFree(q);
+        if (have) (void)hipSetDevice(cur);
+    });
+}
+
+// Batched program copies on one device: a non-blocking stream and two pinned
+// staging buffers that host copies and DMA alternate between (made on first
+// use, kept until the process ends).
+constexpr size_t kStageBytes = size_t(4) << 20;
+
+struct CopyLane {
+    std::mutex mu;
+    hipStream_t stream = nullptr;
+    void *stage[2] = {nullptr, nullptr};
+    hipEvent_t free[2] = {nullptr, nullptr};  // the last copy out of stage[b] is done
+
+    hipError_t init()
+    {
+        hipError_t e = hipSuccess;
+        if (!stream) e = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
+        for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+            if (!stage[b]) e = hipHostMalloc(&stage[b], kStageBytes, 0);
+            if (e == hipSuccess && !free[b]) e = hipEventCreateWithFlags(&free[b], hipEventDisableTiming);
+        }
+        return e;
+    }
+};
+
+// Image sink into a host vector.
+struct VecSink {
+    std::vector<int32_t> v;
+    void put(const int32_t *p, size_t n) { v.insert(v.end(), p, p + n); }
+    void zeros(size_t n) { v.resize(v.size() + n, 0); }
+};
+
+// Image sink that writes a device range through a lane's staging buffers:
+// host writes fill one buffer while the DMA empties the other.  The lane's
+// mutex must be held from the first write to finish().
+struct StagedSink {
+    CopyLane &L;
+    char *dev;
+    size_t at = 0, fill = 0, flushes = 0;
+    int b = 0;
+    hipError_t e = hipSuccess;
+
+    void bytes(const void *p, size_t n)
+    {
+        const char *c = static_cast<const char *>(p);
+        while (n && e == hipSuccess) {
+            const size_t m = std::min(n, kStageBytes - fill);
+            char *s = static_cast<char *>(L.stage[b]) + fill;
+            if (c) {
+                std::memcpy(s, c, m);
+                c += m;
+            } else {
+                std::memset(s, 0, m);
+            }
+            fill += m;
+            n -= m;
+            if (fill == kStageBytes) flush();
+        }
+    }
+    void put(const int32_t *p, size_t n) { bytes(p, n * sizeof(int32_t)); }
+    void zeros(size_t n) { bytes(nullptr, n * sizeof(int32_t)); }
+    void pad_to(size_t align)
+    {
+        const size_t pos = at + fill;
+        bytes(nullptr, align_up(pos, align) - pos);
+    }
+
+    void flush()
+    {
+        if (!fill || e != hipSuccess) return;
+        e = hipMemcpyAsync(dev + at, L.stage[b], fill, hipMemcpyHostToDevice, L.stream);
+        if (e == hipSuccess) e = hipEventRecord(L.free[b], L.stream);
+        at += fill;
+        fill = 0;
+        b ^= 1;
+        // buffer b was last emptied by the flush before this one
+        if (e == hipSuccess && ++flushes >= 2) e = hipEventSynchronize(L.free[b]);
+    }
+
+    hipError_t finish()
+    {
+        flush();
+        const hipError_t s = hipStreamSynchronize(L.stream);
+        return e != hipSuccess ? e : s;
+    }
+};
+
+CopyLane &copy_lane(int d)
+{
+    static std::mutex m;
+    static std::map<int, CopyLane *> *lanes = new std::map<int, CopyLane *>;
+    std::lock_guard<std::mutex> lk(m);
+    CopyLane *&l = (*lanes)[d];
+    if (!l) l = new CopyLane;
+    return *l;
+}
+
 // Device copy of one lane view's tile programs.
 struct DevProgs {
     int device = -1;
-    int32_t *hdrs = nullptr;  // inside the allocation of ops, after the entries
+    int32_t *hdrs = nullptr;  // after the entries, in the same block
     int4 *ops = nullptr;
+    std::shared_ptr<void> mem;  // the block (may hold other views' programs too)
 };
 
 // One lane view's tile programs, shared by every plan with the same lane
@@ -143,15 +251,67 @@ struct ViewProgs {
     std::mutex mu;
     std::deque<DevProgs> dev;
 
-    ~ViewProgs()
+    // Device copy on device d, or null (with mu held).
+    const DevProgs *find(int d) const
     {
-        for (DevProgs &d : dev) {
-            int cur = 0;
-            const bool have = hipGetDevice(&cur) == hipSuccess;
-            (void)hipSetDevice(d.device);
-            if (d.ops) (void)hipFree(d.ops);  // headers share the allocation
-            if (have) (void)hipSetDevice(cur);
+        for (const DevProgs &x : dev)
+            if (x.device == d) return &x;
+        return nullptr;
+    }
+
+    bool on_device(int d)
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        return find(d) != nullptr;
+    }
+
+    // The device image, written to `out` (put(ints, n), zeros(n)): every
+    // pass's entries (program headers point at them by index), spare zero
+    // entries (the first pass fetches entries [first, first + 64) of a
+    // program before it knows its length), then the headers.  *n_ops: ints
+    // before the headers.
+    template <typename Sink>
+    void write_image(Sink &out, size_t *n_ops) const
+    {
+        size_t ops = 0;
+        for (const fht::Pass &ps : plan.passes) {
+            out.put(ps.ops.data(), ps.ops.size());
+            ops += ps.ops.size();
         }
+        out.zeros(4 * fht::kEntryPrefetch);
+        *n_ops = ops + 4 * fht::kEntryPrefetch;
+        int op_base = 0;
+        for (const fht::Pass &ps : plan.passes) {
+            int32_t h[fht::kHdrInts];
+            for (size_t i = 0; i < ps.hdrs.size(); i += fht::kHdrInts) {
+                std::copy(ps.hdrs.begin() + i, ps.hdrs.begin() + i + fht::kHdrInts, h);
+                h[fht::kHdrFirst] += op_base;
+                out.put(h, fht::kHdrInts);
+            }
+            op_base += static_cast<int>(ps.ops.size() / 4);
+        }
+    }
+
+    size_t image_ints() const
+    {
+        size_t n = 4 * fht::kEntryPrefetch;
+        for (const fht::Pass &ps : plan.passes) n += ps.ops.size() + ps.hdrs.size();
+        return n;
+    }
+
+    // Records a copy of image() at `at` (16-byte aligned) in block `mem` on
+    // device d, unless one is there already.
+    const DevProgs *adopt(int d, int32_t *at, size_t n_ops, const std::shared_ptr<void> &mem)
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (const DevProgs *x = find(d)) return x;
+        DevProgs x;
+        x.device = d;
+        x.ops = reinterpret_cast<int4 *>(at);
+        x.hdrs = at + n_ops;
+        x.mem = mem;
+        dev.push_back(x);
+        return &dev.back();
     }
 
     fht_status device_progs(const DevProgs **out)
@@ -159,39 +319,21 @@ struct ViewProgs {
         int d = -1;
         hipError_t e = hipGetDevice(&d);
         if (e != hipSuccess) return hip_status(e);
-        std::lock_guard<std::mutex> lk(mu);
-        for (const DevProgs &x : dev)
-            if (x.device == d) {
-                *out = &x;
-                return FHT_OK;
-            }
-        std::vector<int32_t> hdrs, ops;
-        for (const fht::Pass &ps : plan.passes) {
-            const int op_base = static_cast<int>(ops.size() / 4);
-            for (size_t i = 0; i < ps.hdrs.size(); i += fht::kHdrInts) {
-                hdrs.insert(hdrs.end(), ps.hdrs.begin() + i, ps.hdrs.begin() + i + fht::kHdrInts);
-                hdrs[hdrs.size() - fht::kHdrInts] += op_base;
-            }
-            ops.insert(ops.end(), ps.ops.begin(), ps.ops.end());
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if ((*out = find(d))) return FHT_OK;
         }
-        // spare zero entries: the first pass fetches entries [first, first + 64)
-        // of a program before it knows the program's length
-        ops.resize(ops.size() + 4 * fht::kEntryPrefetch, 0);
-        DevProgs x;
-        x.device = d;
-        // headers and entries in one allocation (entries first: 16-byte aligned)
-        const size_t n_ops = ops.size();
-        ops.insert(ops.end(), hdrs.begin(), hdrs.end());
+        size_t n_ops = 0;
+        VecSink img;
+        img.v.reserve(image_ints());
+        write_image(img, &n_ops);
         int32_t *o = nullptr;
-        e = upload(ops, &o);
+        e = upload(img.v, &o);
         if (e != hipSuccess) {
             if (o) (void)hipFree(o);
             return hip_status(e);
         }
-        x.ops = reinterpret_cast<int4 *>(o);
-        x.hdrs = o + n_ops;
-        dev.push_back(x);
-        *out = &dev.back();
+        *out = adopt(d, o, n_ops, device_block(o, d));
         return FHT_OK;
     }
 
@@ -978,6 +1120,58 @@ fht_status fht_plan_upload_programs(fht_plan plan)
         const DevProgs *p = nullptr;
         const fht_status st = plan->view[v]->device_progs(&p);
         if (st != FHT_OK) return st;
+    }
+    return FHT_OK;
+}
+
+fht_status fht_plan_upload_programs_many(const fht_plan *plans, int32_t n)
+{
+    if (n < 0 || (n > 0 && !plans)) return FHT_EINVAL;
+    for (int32_t i = 0; i < n; ++i)
+        if (!plans[i]) return FHT_EINVAL;
+    int count = 0, d = -1;
+    if (hipGetDeviceCount(&count) != hipSuccess || count == 0) return FHT_ENODEV;
+    hipError_t e = hipGetDevice(&d);
+    if (e != hipSuccess) return hip_status(e);
+    try {
+        // distinct lane views without a copy on this device
+        std::vector<std::shared_ptr<ViewProgs>> views;
+        for (int32_t i = 0; i < n; ++i)
+            for (int v = 0; v < 2; ++v) {
+                const std::shared_ptr<ViewProgs> &vp = plans[i]->view[v];
+                if (vp && std::find(views.begin(), views.end(), vp) == views.end() &&
+                    !vp->on_device(d))
+                    views.push_back(vp);
+            }
+        if (views.empty()) return FHT_OK;
+        // every view's image (256-byte aligned) in one allocation, written
+        // through the staging buffers in one pass
+        std::vector<size_t> n_ops(views.size()), off(views.size());
+        size_t total = 0;
+        for (size_t k = 0; k < views.size(); ++k) {
+            off[k] = total;
+            total += align_up(views[k]->image_ints() * sizeof(int32_t), 256);
+        }
+        void *block = nullptr;
+        e = hipMalloc(&block, total);
+        if (e != hipSuccess) return hip_status(e);
+        const std::shared_ptr<void> mem = device_block(block, d);
+        {
+            CopyLane &L = copy_lane(d);
+            std::lock_guard<std::mutex> lk(L.mu);
+            if ((e = L.init()) != hipSuccess) return hip_status(e);
+            StagedSink out{L, static_cast<char *>(block)};
+            for (size_t k = 0; k < views.size(); ++k) {
+                out.pad_to(256);
+                views[k]->write_image(out, &n_ops[k]);
+            }
+            if ((e = out.finish()) != hipSuccess) return hip_status(e);
+        }
+        for (size_t k = 0; k < views.size(); ++k)
+            views[k]->adopt(d, reinterpret_cast<int32_t *>(static_cast<char *>(block) + off[k]),
+                            n_ops[k], mem);
+    } catch (const std::bad_alloc &) {
+        return FHT_ENOMEM;
     }
     return FHT_OK;
 }

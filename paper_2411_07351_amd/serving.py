@@ -3,9 +3,10 @@
 Each request brings one image (uint8 edge map or float32, any size) and gets
 its four quadrant Hough images back, left on the device.  The loop:
 
-1. plans every arriving request on a pool of host threads (the planner is
-   host code and the ctypes calls release the GIL), with an LRU cache of
-   plans by shape, dtype and split;
+1. plans every arriving request on the library's native planner pool
+   (``fht_planner``: C++ worker threads that also copy the plan's programs to
+   the device, so the loop only submits and polls and never shares the GIL
+   with planning), with an LRU cache of plans by shape, dtype and split;
 2. admits planned requests first come, first served, while their device
    footprint (image, outputs, workspace and work-list tables) fits the HBM
    budget; a request larger than the whole budget is rejected, not crashed;
@@ -28,7 +29,6 @@ from __future__ import annotations
 import threading
 import time
 from collections import OrderedDict, deque
-from concurrent.futures import Future, ThreadPoolExecutor
 from dataclasses import dataclass
 from typing import Any, Sequence
 
@@ -104,43 +104,72 @@ def footprint(plan, kind: str) -> int:
             + px + (64 << 10))
 
 
+class PlanFuture:
+    """A plan being made by the native planner pool (``done()`` polls it,
+    ``result()`` waits for it), shared by every request of its shape."""
+
+    def __init__(self, cache: "PlanCache", ticket: int, args: tuple):
+        self._cache, self._ticket, self._args = cache, ticket, args
+        self._plan = None
+        self._error: Exception | None = None
+
+    def done(self) -> bool:
+        with self._cache._lock:
+            if self._plan is None and self._error is None:
+                state, h, st = B.fht_planner_poll(self._cache._pool, self._ticket)
+                if state == 0:
+                    return False
+                if state < 0:
+                    self._error = RuntimeError(f"planner ticket {self._ticket} is unknown")
+                elif st != 0:
+                    self._error = B.FhtError(st, "fht_plan_create")
+                else:
+                    rows, cols, kind, split = self._args
+                    self._plan = B.Plan.adopt(h, rows, cols, kind, split)
+            return True
+
+    def result(self):
+        while not self.done():
+            time.sleep(20e-6)
+        if self._error is not None:
+            raise self._error
+        return self._plan
+
+
 class PlanCache:
-    """Plans made on host threads, cached (LRU) by shape, dtype and split.
-    `prepare(plan)`, if given, runs on the planner thread after planning (the
-    GPU executor copies the plan's tables to the device there, so that the
-    serving loop never waits for it)."""
+    """Plans made by the library's native planner pool, cached (LRU) by shape,
+    dtype and split.  With ``device`` >= 0 the pool also copies each plan's
+    programs to that HIP device, on its own threads."""
 
     def __init__(self, threads: int = 8, capacity: int = 256, schedule: dict | None = None,
-                 prepare=None):
-        self._pool = ThreadPoolExecutor(max_workers=max(1, threads),
-                                        thread_name_prefix="fht-plan")
+                 device: int = -1):
+        self._pool = B.fht_planner_create(max(1, min(int(threads), 256)), int(device))
         self._lru: OrderedDict = OrderedDict()
         self._lock = threading.Lock()
         self._capacity = capacity
-        self._schedule = schedule
-        self._prepare = prepare
+        self._schedule = B.fht_schedule(**schedule) if schedule else None
 
-    def _make(self, rows: int, cols: int, kind: str, split: str):
-        plan = B.Plan(rows, cols, kind, split, schedule=self._schedule)
-        if self._prepare is not None:
-            self._prepare(plan)
-        return plan
-
-    def get(self, rows: int, cols: int, kind: str, split: str) -> Future:
+    def get(self, rows: int, cols: int, kind: str, split: str) -> PlanFuture:
         key = (rows, cols, kind, split)
         with self._lock:
             fut = self._lru.get(key)
             if fut is not None:
                 self._lru.move_to_end(key)
                 return fut
-            fut = self._pool.submit(self._make, rows, cols, kind, split)
+            ticket = B.fht_planner_submit(self._pool, rows, cols, B._dtype_code(kind),
+                                          B._split_code(split), 15, self._schedule)
+            fut = PlanFuture(self, ticket, key)
             self._lru[key] = fut
             while len(self._lru) > self._capacity:
                 self._lru.popitem(last=False)
             return fut
 
     def close(self) -> None:
-        self._pool.shutdown(wait=True)
+        """Stops the pool (plans already taken stay valid)."""
+        with self._lock:
+            pool, self._pool = self._pool, None
+        if pool:
+            B.fht_planner_destroy(pool)
 
 
 class WallClock:
@@ -185,11 +214,10 @@ class GpuExecutor:
     def n_streams(self) -> int:
         return len(self.streams)
 
-    def prepare(self, plan) -> None:
-        """Copy a plan's lane-view programs (what batches read) to the device,
-        on a planner thread."""
-        with self.torch.cuda.device(self.device):
-            B.fht_plan_upload_programs(plan.handle)
+    @property
+    def plan_device(self) -> int:
+        """Device the planner pool copies plan programs to."""
+        return self.device.index
 
     def launch(self, reqs: Sequence[Request], slot: int) -> dict:
         torch = self.torch
@@ -267,7 +295,7 @@ class Server:
         self.clock = clock or WallClock()
         self.keep_outputs = keep_outputs
         self.plans = PlanCache(plan_threads, plan_cache, schedule,
-                               getattr(executor, "prepare", None))
+                               getattr(executor, "plan_device", -1))
         self.in_use = 0
         self.peak_in_use = 0
         self.peak_running = 0

@@ -2,6 +2,10 @@
 import ctypes
 import os
 import re
+import time
+
+import numpy as np
+import pytest
 
 import paper_2411_07351_amd as F
 
@@ -62,3 +66,83 @@ def test_null_arguments_are_rejected():
     assert lib.fht_plan_upload_programs(None) == -1
     F.fht_plan_destroy(None)
     F.fht_batch_destroy(None)
+
+
+def _wait(pool, ticket, timeout=60.0):
+    t0 = time.monotonic()
+    while True:
+        state, h, st = F.fht_planner_poll(pool, ticket)
+        if state != 0:
+            return state, h, st
+        assert time.monotonic() - t0 < timeout, "planner pool never finished"
+        time.sleep(1e-3)
+
+
+def _tables(h):
+    out = []
+    for v in (0, 1):
+        for p in range(max(F.fht_plan_num_passes(h, v), 0)):
+            t = F.fht_plan_pass_tables(h, v, p)
+            out += [np.ascontiguousarray(t[k]).tobytes() for k in ("hdrs", "ops", "items")]
+    return out
+
+
+def test_planner_pool_makes_the_same_plans():
+    """Plans from the native pool (host only) equal plans made directly."""
+    pool = F.fht_planner_create(4, -1)
+    try:
+        shapes = [(64, 80, F.FHT_U8, 0), (1021, 333, F.FHT_F32, 1), (7, 3000, F.FHT_U8, 0),
+                  (300, 300, F.FHT_F64, 0)] * 3
+        tickets = [F.fht_planner_submit(pool, r, c, d, s) for r, c, d, s in shapes]
+        assert tickets == list(range(len(shapes)))
+        for (r, c, d, s), t in zip(shapes, tickets):
+            state, h, st = _wait(pool, t)
+            assert state == 1 and st == 0 and h
+            ref = F.fht_plan_create(r, c, d, s, 15, None)
+            try:
+                assert F.fht_plan_out_elems(h) == F.fht_plan_out_elems(ref)
+                assert _tables(h) == _tables(ref)
+            finally:
+                F.fht_plan_destroy(ref)
+                F.fht_plan_destroy(h)
+            assert F.fht_planner_poll(pool, t)[0] == -1  # taken once
+        assert F.fht_planner_poll(pool, len(shapes))[0] == -1  # never issued
+    finally:
+        F.fht_planner_destroy(pool)
+
+
+def test_planner_pool_errors():
+    with pytest.raises(F.FhtError):
+        F.fht_planner_create(0, -1)
+    with pytest.raises(F.FhtError):
+        F.fht_planner_create(2, -2)
+    pool = F.fht_planner_create(2, -1)
+    try:
+        state, h, st = _wait(pool, F.fht_planner_submit(pool, 0, 5, F.FHT_U8, 0))
+        assert state == 1 and F.STATUS[st] == "FHT_EINVAL" and not h
+        state, h, st = _wait(pool, F.fht_planner_submit(pool, 5, 5, 9, 0))
+        assert state == 1 and st != 0 and not h
+    finally:
+        F.fht_planner_destroy(pool)
+    # a pool destroyed with work queued drops it and frees unpolled plans
+    pool = F.fht_planner_create(1, -1)
+    for _ in range(20):
+        F.fht_planner_submit(pool, 4000, 4000, F.FHT_U8, 0)
+    F.fht_planner_destroy(pool)
+    F.fht_planner_destroy(None)
+    lib = ctypes.CDLL(F.LIB_PATH)
+    lib.fht_planner_poll.restype = ctypes.c_int32
+    lib.fht_planner_poll.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                     ctypes.c_void_p]
+    assert lib.fht_planner_poll(None, 0, None, None) == -1
+
+
+def test_planner_pool_without_a_device_reports_it():
+    """device >= 0 on a host without that HIP device: every plan's poll
+    reports FHT_ENODEV (the pool itself is created)."""
+    pool = F.fht_planner_create(2, 250)
+    try:
+        state, h, st = _wait(pool, F.fht_planner_submit(pool, 64, 64, F.FHT_U8, 0))
+        assert state == 1 and F.STATUS[st] == "FHT_ENODEV" and not h
+    finally:
+        F.fht_planner_destroy(pool)

@@ -256,3 +256,45 @@ def test_random_shapes_every_path(F, kind):
             tol = 1e-5 if kind == "f32" else 1e-12
             for g, q in zip(got, qs):
                 _assert_float_close(g, ref[q], ab[q], tol)
+
+
+def test_planner_pool_plans_on_the_device(F):
+    """Plans from the native planner pool, their programs copied by its
+    uploader in batched copies (fht_plan_upload_programs_many), run a ragged
+    batch bit-exactly (a schedule of their own, so no earlier test has put
+    these lane views on the device)."""
+    import time
+    rng = WL.rng_for(3, salt=9)
+    imgs_np = WL.ragged_edge_maps(rng, 10, 2, 400)
+    sched = F.fht_schedule(s_tile=128, s_tile_first=64, first_levels=4, max_levels=3,
+                           lds_budget=64 * 1024, t_tile=8, threads=512, threads_first=512)
+    pool = F.fht_planner_create(4, torch.cuda.current_device())
+    try:
+        tickets = [F.fht_planner_submit(pool, i.shape[0], i.shape[1], F.FHT_U8, 0, 15, sched)
+                   for i in imgs_np]
+        plans = []
+        for t in tickets:
+            t0 = time.monotonic()
+            while True:
+                state, h, st = F.fht_planner_poll(pool, t)
+                if state:
+                    break
+                assert time.monotonic() - t0 < 60
+                time.sleep(1e-3)
+            assert state == 1 and st == 0
+            plans.append(h)
+    finally:
+        F.fht_planner_destroy(pool)
+    wrapped = [F.Plan.adopt(h, i.shape[0], i.shape[1], "u8", "S") for h, i in zip(plans, imgs_np)]
+    F.fht_plan_upload_programs_many([p.handle for p in wrapped])  # all there: nothing to copy
+    imgs = [torch.from_numpy(i).cuda() for i in imgs_np]
+    outs = [p.new_out() for p in wrapped]
+    batch = F.Batch(wrapped, imgs, outs, defer_upload=True)
+    tables = torch.empty(batch.tables_bytes, dtype=torch.uint8, device="cuda")
+    batch.upload(tables)
+    batch.run(batch.new_ws())
+    torch.cuda.synchronize()
+    for img_np, p, out in zip(imgs_np, wrapped, outs):
+        ref = native.hough4_u8(img_np, 0)
+        for q, g in enumerate(p.split_out(out)):
+            assert (g.cpu().numpy() == ref[q]).all(), (img_np.shape, q)

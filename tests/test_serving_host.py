@@ -168,6 +168,8 @@ def test_failed_batch_is_retried_per_request():
     ex = FakeExecutor(clock)
     ex.fail = 1
     srv = S.Server(ex, 1 << 40, clock=clock, max_batch_images=8)
+    for r in reqs:  # planned up front, so the first (failing) batch holds several requests
+        srv.plans.get(r.rows, r.cols, r.kind, r.split).result()
     srv.run(reqs)
     srv.close()
     assert all(r.status == "done" for r in reqs)
