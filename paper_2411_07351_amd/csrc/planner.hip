@@ -163,8 +163,13 @@ fht_status fht_planner_submit(fht_planner pl, int32_t rows, int32_t cols, fht_dt
     try {
         std::lock_guard<std::mutex> lk(pl->mu);
         t.ticket = pl->next;
-        pl->pending.insert(t.ticket);
         pl->queue.push_back(t);
+        try {
+            pl->pending.insert(t.ticket);
+        } catch (...) {
+            pl->queue.pop_back();
+            throw;
+        }
         ++pl->next;
     } catch (...) {
         return FHT_ENOMEM;
