@@ -275,6 +275,14 @@ fht_status fht_batch_upload(fht_batch batch, void *d_tables, size_t bytes, void 
 fht_status fht_batch_upload_staged(fht_batch batch, void *d_tables, size_t bytes,
                                    void *h_staging, void *stream);
 
+/* Enqueues on `stream` the copies of the batch's images from srcs[i], one
+ * entry per image of the batch (host memory, pinned for an asynchronous copy,
+ * or device memory; NULL: image i is in place already) to the device images the batch was made with, rows x cols
+ * pixels of its dtype each, in one call for the whole batch.  srcs must stay
+ * valid and unchanged until the stream has passed the copies.  Errors:
+ * FHT_EINVAL, FHT_EHIP (copies enqueued before the failing one stay). */
+fht_status fht_batch_copy_images(fht_batch batch, const void *const *srcs, void *stream);
+
 /*
  * Adjoint (back-projection) of fht_forward for float32/float64 plans: the
  * image gradient of a scalar function of the output, given its output

@@ -40,7 +40,7 @@ __all__ = [
     "fht_forward_many", "fht_plan_adjoint_workspace_bytes_many", "fht_adjoint_many",
     "fht_plan_adjoint_num_passes", "fht_plan_adjoint_pass", "fht_batch_upload_staged",
     "fht_plan_upload_programs", "fht_planner_create", "fht_planner_submit", "fht_planner_poll",
-    "fht_planner_destroy", "fht_plan_upload_programs_many", "STATUS",
+    "fht_planner_destroy", "fht_plan_upload_programs_many", "fht_batch_copy_images", "STATUS",
 ]
 
 FHT_U8, FHT_F32, FHT_F64 = 0, 1, 2
@@ -64,7 +64,7 @@ EXPORTED = (
     "fht_adjoint_many", "fht_plan_adjoint_num_passes", "fht_plan_adjoint_pass",
     "fht_batch_upload_staged", "fht_plan_upload_programs",
     "fht_planner_create", "fht_planner_submit", "fht_planner_poll", "fht_planner_destroy",
-    "fht_plan_upload_programs_many",
+    "fht_plan_upload_programs_many", "fht_batch_copy_images",
 )
 
 # struct fht_peak
@@ -125,6 +125,7 @@ _sig("fht_batch_upload", _i32, _vp, _vp, _sz, _vp)
 _sig("fht_debug_fail_next", None, _i32, _i32)
 _sig("fht_batch_upload_staged", _i32, _vp, _vp, _sz, _vp, _vp)
 _sig("fht_plan_upload_programs", _i32, _vp)
+_sig("fht_batch_copy_images", _i32, _vp, ctypes.POINTER(_vp), _vp)
 _sig("fht_plan_upload_programs_many", _i32, ctypes.POINTER(_vp), _i32)
 _sig("fht_planner_create", _i32, _i32, _i32, ctypes.POINTER(_vp))
 _sig("fht_planner_submit", _i32, _vp, _i32, _i32, _i32, _i32, _u32, ctypes.POINTER(fht_schedule),
@@ -296,6 +297,11 @@ def fht_batch_prepare(plans: Sequence[int], d_imgs: Sequence[int], d_outs: Seque
     _check(_lib.fht_batch_prepare(ctypes.byref(h), arr(*plans), n, arr(*d_imgs), arr(*d_outs)),
            "fht_batch_prepare")
     return h.value
+
+
+def fht_batch_copy_images(batch: int, srcs: Sequence, stream: int | None) -> None:
+    arr = (_vp * len(srcs))(*srcs)
+    _check(_lib.fht_batch_copy_images(batch, arr, stream), "fht_batch_copy_images")
 
 
 def fht_batch_tables_bytes(batch: int) -> int:
@@ -662,6 +668,30 @@ class Batch:
         self.num_launches = fht_batch_num_launches(self.handle)
         self.tables_bytes = fht_batch_tables_bytes(self.handle)
         self.tables = None
+
+    @classmethod
+    def from_pointers(cls, plans: Sequence[Plan], img_ptrs: Sequence[int],
+                      out_ptrs: Sequence[int]) -> "Batch":
+        """A deferred-upload batch over raw device pointers (image i: rows x
+        cols pixels of its plan's dtype, output i: ``out_elems`` elements of
+        its output dtype), for callers that manage the buffers themselves;
+        nothing checks their sizes.  The caller keeps the buffers alive."""
+        if not (len(plans) == len(img_ptrs) == len(out_ptrs)) or not plans:
+            raise ValueError("plans, images and outputs must be non-empty and of equal length")
+        self = cls.__new__(cls)
+        self.plans = list(plans)
+        self.imgs = self.outs = None
+        self.handle = fht_batch_prepare([p.handle for p in plans], list(img_ptrs), list(out_ptrs))
+        self.ws_bytes = fht_batch_workspace_bytes(self.handle)
+        self.num_launches = fht_batch_num_launches(self.handle)
+        self.tables_bytes = fht_batch_tables_bytes(self.handle)
+        self.tables = None
+        return self
+
+    def copy_images(self, srcs: Sequence, stream=None) -> None:
+        """Enqueue the copies of every image from srcs[i] (a pinned host or a
+        device address; None: in place) in one call."""
+        fht_batch_copy_images(self.handle, srcs, _stream_handle(stream))
 
     def upload(self, tables, stream=None, staging=None) -> None:
         """Enqueue the copy of the device tables into `tables` (a device tensor

@@ -684,6 +684,7 @@ struct fht_batch_s {
         size_t ws_base;
     };
     std::vector<Pending> pending;
+    std::vector<std::pair<void *, size_t>> images;  // device image and its bytes, per image
     std::vector<size_t> off_items;  // per launch
     char *dev = nullptr;            // device copy of the blob (null until uploaded)
     bool owns = false;              // dev was allocated by the library
@@ -1227,11 +1228,27 @@ fht_status fht_batch_prepare(fht_batch *out, const fht_plan *plans, int32_t n,
     b->dtype = plans[0]->dtype;
     try {
         batch_prepare(b, plans, n, d_imgs, d_outs);
+        const size_t px_bytes = b->dtype == FHT_U8 ? 1 : acc_bytes(b->dtype);
+        for (int32_t i = 0; i < n; ++i)
+            b->images.emplace_back(const_cast<void *>(d_imgs[i]),
+                                   static_cast<size_t>(plans[i]->R) * plans[i]->C * px_bytes);
     } catch (const std::bad_alloc &) {
         delete b;
         return FHT_ENOMEM;
     }
     *out = b;
+    return FHT_OK;
+}
+
+fht_status fht_batch_copy_images(fht_batch batch, const void *const *srcs, void *stream)
+{
+    if (!batch || !srcs) return FHT_EINVAL;
+    for (size_t i = 0; i < batch->images.size(); ++i) {
+        if (!srcs[i]) continue;
+        const hipError_t e = hipMemcpyAsync(batch->images[i].first, srcs[i], batch->images[i].second,
+                                            hipMemcpyDefault, static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) return hip_status(e);
+    }
     return FHT_OK;
 }
 

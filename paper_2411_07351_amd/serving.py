@@ -40,6 +40,10 @@ _IN_BYTES = {"u8": 1, "f32": 4, "f64": 8}
 _OUT_BYTES = {"u8": 4, "f32": 4, "f64": 8}
 
 
+def _align(n: int, a: int = 256) -> int:
+    return (n + a - 1) // a * a
+
+
 def _kind(image) -> str:
     name = str(image.dtype)
     if "uint8" in name:
@@ -220,29 +224,39 @@ class GpuExecutor:
         return self.device.index
 
     def launch(self, reqs: Sequence[Request], slot: int) -> dict:
+        """Enqueues one batch: one device buffer for its images and one for
+        its outputs (256-byte aligned slices), the image copies in one call,
+        the tables through pinned staging, then the fused passes."""
         torch = self.torch
         stream = self.streams[slot]
         with torch.cuda.stream(stream):
-            imgs = []
+            img_off, out_off, ib, ob = [], [], 0, 0
+            srcs, held = [], []
             for r in reqs:
+                img_off.append(ib)
+                ib += _align(r.pixels * _IN_BYTES[r.kind])
+                out_off.append(ob)
+                ob += _align(r.plan.out_elems * _OUT_BYTES[r.kind])
                 img = r.image
                 if isinstance(img, np.ndarray):
                     img = torch.from_numpy(img)
-                if img.device != self.device:
-                    dev = torch.empty(tuple(img.shape), dtype=img.dtype, device=self.device)
-                    dev.copy_(img, non_blocking=True)
-                    img = dev
-                imgs.append(img.contiguous())
-            outs = [r.plan.new_out(self.device) for r in reqs]
-            batch = B.Batch([r.plan for r in reqs], imgs, outs, defer_upload=True)
+                img = img.contiguous()
+                held.append(img)
+                srcs.append(img.data_ptr())
+            imgs = torch.empty(max(ib, 1), dtype=torch.uint8, device=self.device)
+            outs = torch.empty(max(ob, 1), dtype=torch.uint8, device=self.device)
+            ip, op = imgs.data_ptr(), outs.data_ptr()
+            batch = B.Batch.from_pointers([r.plan for r in reqs], [ip + o for o in img_off],
+                                          [op + o for o in out_off])
             ws = torch.empty(max(batch.ws_bytes, 1), dtype=torch.uint8, device=self.device)
             tables = torch.empty(batch.tables_bytes, dtype=torch.uint8, device=self.device)
             # pinned staging: the table copy is asynchronous, so the loop never
             # waits here for the batches already on the stream
             staging = torch.empty(batch.tables_bytes, dtype=torch.uint8, pin_memory=True)
-            h = {"batch": batch, "imgs": imgs, "outs": outs, "ws": ws, "tables": tables,
-                 "staging": staging}
+            h = {"batch": batch, "imgs": imgs, "outs": outs, "out_off": out_off, "reqs": list(reqs),
+                 "held": held, "ws": ws, "tables": tables, "staging": staging}
             try:
+                batch.copy_images(srcs, stream)
                 batch.upload(tables, stream, staging)
                 batch.run(ws, stream)
             except B.FhtError:
@@ -261,7 +275,13 @@ class GpuExecutor:
         return h["event"].query()
 
     def outputs(self, h) -> list:
-        return h["outs"]
+        """Each request's flat output: a view of the batch's output buffer
+        (which it keeps alive)."""
+        outs, res = h["outs"], []
+        for r, o in zip(h["reqs"], h["out_off"]):
+            n = r.plan.out_elems * _OUT_BYTES[r.kind]
+            res.append(outs[o:o + n].view(r.plan.out_dtype))
+        return res
 
     def release(self, h) -> None:
         h.clear()
@@ -388,7 +408,8 @@ class Server:
             # completions
             for f in list(self.inflight):
                 if self.executor.done(f.handle):
-                    outs = self.executor.outputs(f.handle) or [None] * len(f.reqs)
+                    outs = (self.executor.outputs(f.handle) if self.keep_outputs else None) \
+                        or [None] * len(f.reqs)
                     for r, o in zip(f.reqs, outs):
                         self._finish(r, "done", now)
                         r.out = o if self.keep_outputs else None

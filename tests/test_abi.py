@@ -64,6 +64,13 @@ def test_null_arguments_are_rejected():
     lib.fht_plan_upload_programs.restype = ctypes.c_int32
     lib.fht_plan_upload_programs.argtypes = [ctypes.c_void_p]
     assert lib.fht_plan_upload_programs(None) == -1
+    lib.fht_batch_copy_images.restype = ctypes.c_int32
+    lib.fht_batch_copy_images.argtypes = [ctypes.c_void_p] * 3
+    assert lib.fht_batch_copy_images(None, None, None) == -1
+    lib.fht_plan_upload_programs_many.restype = ctypes.c_int32
+    lib.fht_plan_upload_programs_many.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    assert lib.fht_plan_upload_programs_many(None, 1) == -1
+    assert lib.fht_plan_upload_programs_many(None, -1) == -1
     F.fht_plan_destroy(None)
     F.fht_batch_destroy(None)
 
