@@ -298,3 +298,46 @@ def test_planner_pool_plans_on_the_device(F):
         ref = native.hough4_u8(img_np, 0)
         for q, g in enumerate(p.split_out(out)):
             assert (g.cpu().numpy() == ref[q]).all(), (img_np.shape, q)
+
+
+def test_batch_over_pointers_with_image_copies(F):
+    """Batch.from_pointers over one image and one output buffer, images
+    copied by fht_batch_copy_images from pinned host memory, from device
+    memory and in place (NULL), bit-exact against the oracle."""
+    rng = WL.rng_for(3, salt=11)
+    imgs_np = WL.ragged_edge_maps(rng, 6, 3, 300)
+    plans = [F.Plan(i.shape[0], i.shape[1], "u8", "S") for i in imgs_np]
+    align = lambda n: (n + 255) // 256 * 256
+    img_off, out_off, ib, ob = [], [], 0, 0
+    for i, p in zip(imgs_np, plans):
+        img_off.append(ib)
+        ib += align(i.size)
+        out_off.append(ob)
+        ob += align(p.out_elems * 4)
+    ibuf = torch.zeros(ib, dtype=torch.uint8, device="cuda")
+    obuf = torch.empty(ob, dtype=torch.uint8, device="cuda")
+    srcs, held = [], []
+    for k, (i, o) in enumerate(zip(imgs_np, img_off)):
+        t = torch.from_numpy(i)
+        if k % 3 == 0:  # pinned host memory
+            t = t.pin_memory()
+        elif k % 3 == 1:  # device memory elsewhere
+            t = t.cuda()
+        else:  # already in place
+            ibuf[o:o + i.size].copy_(t.reshape(-1))
+            t = None
+        held.append(t)
+        srcs.append(None if t is None else t.data_ptr())
+    batch = F.Batch.from_pointers(plans, [ibuf.data_ptr() + o for o in img_off],
+                                  [obuf.data_ptr() + o for o in out_off])
+    stream = torch.cuda.current_stream()
+    batch.copy_images(srcs, stream)
+    tables = torch.empty(batch.tables_bytes, dtype=torch.uint8, device="cuda")
+    batch.upload(tables, stream)
+    batch.run(batch.new_ws(), stream)
+    torch.cuda.synchronize()
+    for i, p, o in zip(imgs_np, plans, out_off):
+        out = obuf[o:o + p.out_elems * 4].view(torch.int32)
+        ref = native.hough4_u8(i, 0)
+        for q, g in enumerate(p.split_out(out)):
+            assert (g.cpu().numpy() == ref[q]).all(), (i.shape, q)
