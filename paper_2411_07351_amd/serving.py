@@ -120,6 +120,9 @@ class PlanFuture:
     def done(self) -> bool:
         with self._cache._lock:
             if self._plan is None and self._error is None:
+                if not self._cache._pool:
+                    self._error = RuntimeError("the plan cache was closed before this plan was taken")
+                    return True
                 state, h, st = B.fht_planner_poll(self._cache._pool, self._ticket)
                 if state == 0:
                     return False

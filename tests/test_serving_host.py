@@ -188,6 +188,22 @@ def test_failure_of_a_lone_request_fails_only_that_request():
     assert sum(r.status == "done" for r in reqs) == 9
 
 
+def test_plan_cache_close_fails_pending_plans_cleanly():
+    cache = S.PlanCache(threads=1, capacity=8)
+    done = cache.get(64, 80, "u8", "S")
+    assert done.result().rows == 64
+    pending = [cache.get(3000 + k, 3000, "u8", "S") for k in range(4)]
+    cache.close()
+    assert done.result().rows == 64  # taken before the close: still valid
+    for f in pending:
+        try:
+            f.result()
+        except RuntimeError as e:
+            assert "closed" in str(e)
+    with pytest.raises(F.FhtError):
+        cache.get(70, 70, "u8", "S")
+
+
 def test_plan_cache_reuses_plans():
     cache = S.PlanCache(threads=2, capacity=2)
     a = cache.get(64, 80, "u8", "S").result()
