@@ -153,3 +153,33 @@ def test_planner_pool_without_a_device_reports_it():
         assert state == 1 and F.STATUS[st] == "FHT_ENODEV" and not h
     finally:
         F.fht_planner_destroy(pool)
+
+
+def test_planner_pool_from_several_threads():
+    """Submits and polls from four threads at once: tickets are unique and
+    every plan arrives exactly once, at the thread that asked for it."""
+    import threading
+    pool = F.fht_planner_create(3, -1)
+    got, errors = {}, []
+
+    def client(k):
+        try:
+            mine = [(F.fht_planner_submit(pool, 40 + 7 * k + j, 90 + j, F.FHT_U8, j % 2), j)
+                    for j in range(15)]
+            for t, j in mine:
+                state, h, st = _wait(pool, t)
+                assert state == 1 and st == 0 and h
+                assert F.fht_plan_out_elems(h) == 2 * 2 * (40 + 7 * k + j) * (90 + j)
+                F.fht_plan_destroy(h)
+                got[t] = k
+        except Exception as e:  # reported below, in the test's thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=client, args=(k,)) for k in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    F.fht_planner_destroy(pool)
+    assert not errors, errors
+    assert sorted(got) == list(range(60))
