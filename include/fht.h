@@ -185,7 +185,10 @@ fht_status fht_plan_upload_programs_many(const fht_plan *plans, int32_t n);
  *   fht_planner_destroy drops queued plans, waits for those being made, frees
  *                       finished plans no poll took, and joins the threads;
  *                       NULL is ignored.
- * Submit and poll may be called from any threads.
+ * Submit and poll may be called from any threads.  With device >= 0 the
+ * uploader allocates device memory and copies on its own stream while plans
+ * arrive: a HIP graph captured meanwhile in global capture mode on another
+ * thread fails, so capture with thread-local mode or while no plan is made.
  */
 fht_status fht_planner_create(int32_t threads, int32_t device, fht_planner *out);
 fht_status fht_planner_submit(fht_planner planner, int32_t rows, int32_t cols, fht_dtype dtype,
