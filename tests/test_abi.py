@@ -183,3 +183,22 @@ def test_planner_pool_from_several_threads():
     F.fht_planner_destroy(pool)
     assert not errors, errors
     assert sorted(got) == list(range(60))
+
+
+def test_program_uploads_without_a_device():
+    """With no HIP device both program uploads report FHT_ENODEV (also for an
+    empty list) and leave the plan usable for host queries."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    h = F.fht_plan_create(64, 80, F.FHT_U8, 0, 15, None)
+    try:
+        for call in (lambda: F.fht_plan_upload_programs(h),
+                     lambda: F.fht_plan_upload_programs_many([h, h]),
+                     lambda: F.fht_plan_upload_programs_many([])):
+            with pytest.raises(F.FhtError) as e:
+                call()
+            assert F.STATUS[e.value.status] == "FHT_ENODEV"
+        assert F.fht_plan_out_elems(h) == 2 * 2 * 64 * 80
+    finally:
+        F.fht_plan_destroy(h)
