@@ -32,15 +32,15 @@ struct Result {
     fht_plan plan;
 };
 
+// Plans per batched copy of the uploader.
+constexpr size_t kUploadGroup = 32;
+
 }  // namespace
 
 // Worker threads only plan (host code); one uploader thread, the only one
 // that calls HIP, copies the programs of up to kUploadGroup finished plans in
 // one allocation and one copy: small allocations and copies from many threads
 // serialise inside the HIP runtime.
-// Plans per batched copy of the uploader.
-constexpr size_t kUploadGroup = 32;
-
 struct fht_planner_s {
     int device = -1;
     std::mutex mu;
