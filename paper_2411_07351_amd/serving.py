@@ -380,7 +380,7 @@ class Server:
         while nxt < len(reqs) or planning or ready or self.admitted or self.inflight:
             now = clock.now()
             busy = False
-            # arrivals -> planner threads
+            # arrivals -> the planner pool
             while nxt < len(reqs) and reqs[nxt].arrival <= now:
                 r = reqs[nxt]
                 nxt += 1
