@@ -182,8 +182,9 @@ fht_status fht_plan_upload_programs_many(const fht_plan *plans, int32_t n);
  *                       is FHT_OK); the ticket is then forgotten.  0 while it
  *                       is queued or being made, -1 for a null argument or a
  *                       ticket never issued or already taken.
- *   fht_planner_destroy drops queued plans, waits for those being made, frees
- *                       finished plans no poll took, and joins the threads;
+ *   fht_planner_destroy drops queued plans, waits for those being made and the
+ *                       copy under way, frees the plans no poll took (finished
+ *                       or waiting for their copy), and joins the threads;
  *                       NULL is ignored.
  * Submit and poll may be called from any threads.  With device >= 0 the
  * uploader allocates device memory and copies on its own stream while plans
