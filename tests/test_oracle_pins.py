@@ -391,3 +391,100 @@ def test_adjoint_pins_reject_a_sign_mistake():
         for t in range(7):
             wrong[x] += G[t][(np.arange(5) + P[t, x]) % 5]
     assert float((A * wrong).sum()) != int((O.hough_lanes(A, O.SPLIT_S) * G).sum())
+
+
+# ------------------------------------------------------------ sampled outputs
+
+SAMPLE_SHAPES = [(7, 3), (3, 7), (13, 11), (5, 17), (23, 6), (1, 9), (9, 1)]
+
+
+def _sample_f64_with(lib, img, split, q, t, s):
+    """Call ``orc_hough_sample_f64`` of the C library ``lib`` (ctypes.CDLL)."""
+    import ctypes
+    img = np.ascontiguousarray(img, dtype=np.float64)
+    q, t, s = (np.ascontiguousarray(v, dtype=np.int32) for v in (q, t, s))
+    out = np.empty(q.shape[0])
+    ab = np.empty_like(out)
+    p = ctypes.c_void_p
+    fn = lib.orc_hough_sample_f64
+    fn.argtypes = [p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64, p, p, p, p, p]
+    rc = fn(p(img.ctypes.data), img.shape[0], img.shape[1], split, q.shape[0],
+            p(q.ctypes.data), p(t.ctypes.data), p(s.ctypes.data), p(out.ctypes.data),
+            p(ab.ctypes.data))
+    assert rc == 0
+    return out, ab
+
+
+def _every_output(R, C):
+    """(q, t, s) of every output of the four quadrants of an R x C image."""
+    qs, ts, ss = [], [], []
+    for q, (W, H) in enumerate(((R, C), (R, C), (C, R), (C, R))):
+        t, s = np.meshgrid(np.arange(W), np.arange(H), indexing="ij")
+        qs.append(np.full(W * H, q))
+        ts.append(t.ravel())
+        ss.append(s.ravel())
+    return np.concatenate(qs), np.concatenate(ts), np.concatenate(ss)
+
+
+def _sampler_matches_full_transform(sample):
+    """The sampled f64 outputs and absolute sums equal those of the whole
+    transform, which the Python oracle pins (Sec. 3 definition), for all four
+    quadrants, both splits, negative pixels, W > H (shifts that wrap more than
+    once) and W < H."""
+    rng = np.random.default_rng(41)
+    for split in SPLITS:
+        for R, C in SAMPLE_SHAPES:
+            img = rng.standard_normal((R, C))
+            q, t, s = _every_output(R, C)
+            got, gab = sample(img, split, q, t, s)
+            ref = O.hough4(img, split)
+            rab = O.hough4(img, split, absolute=True)
+            want = np.array([ref[a][b, c] for a, b, c in zip(q, t, s)])
+            wab = np.array([rab[a][b, c] for a, b, c in zip(q, t, s)])
+            if not (np.allclose(got, want, rtol=0, atol=1e-12) and
+                    np.allclose(gab, wab, rtol=0, atol=1e-12)):
+                return False
+            # and the C whole-image oracle the f32 parity tests use beside it
+            full, fab = native.hough4_f64(img, split)
+            if not (np.allclose(got, [full[a][b, c] for a, b, c in zip(q, t, s)], atol=1e-12) and
+                    np.allclose(gab, [fab[a][b, c] for a, b, c in zip(q, t, s)], atol=1e-12)):
+                return False
+    return True
+
+
+def test_sample_f64_equals_full_transform():
+    assert _sampler_matches_full_transform(lambda *a: native.sample_f64(*a))
+
+
+def test_sample_u8_equals_full_transform_every_output():
+    rng = np.random.default_rng(42)
+    for split in SPLITS:
+        for R, C in SAMPLE_SHAPES:
+            img = rng.integers(0, 256, size=(R, C), dtype=np.uint8)
+            q, t, s = _every_output(R, C)
+            ref = O.hough4(img, split)
+            want = np.array([ref[a][b, c] for a, b, c in zip(q, t, s)])
+            assert (native.sample_u8(img, split, q, t, s) == want).all(), (split, R, C)
+
+
+@pytest.mark.parametrize("mistake", ["sign_flip_columns", "abs_sum_signed"])
+def test_sample_f64_pin_rejects_planted_mistakes(tmp_path, mistake):
+    """Compile a copy of the C oracle with one mistake planted in its f64
+    sampler (CPU only) and check that the pin above fails on it."""
+    import ctypes
+    import subprocess
+    src = open(native._SRC).read()
+    head, tail = src.split("int orc_hough_sample_f64", 1)
+    if mistake == "sign_flip_columns":
+        old = "(int64_t)sigma * pat[x]"
+        new = "(int64_t)(q >= 2 ? -sigma : sigma) * pat[x]"
+    else:
+        old = "aacc += v < 0 ? -v : v;"
+        new = "aacc += v;"
+    assert old in tail
+    (tmp_path / "bad.c").write_text(head + "int orc_hough_sample_f64" + tail.replace(old, new, 1))
+    lib_path = tmp_path / "libbad.so"
+    subprocess.run(["gcc", "-O1", "-std=c99", "-fopenmp", "-shared", "-fPIC", "-o",
+                    str(lib_path), str(tmp_path / "bad.c")], check=True)
+    bad = ctypes.CDLL(str(lib_path))
+    assert not _sampler_matches_full_transform(lambda *a: _sample_f64_with(bad, *a))
