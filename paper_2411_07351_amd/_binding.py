@@ -7,6 +7,9 @@ library has not been built, importing this module raises.
 """
 from __future__ import annotations
 
+import atexit
+import collections
+import contextlib
 import ctypes
 import os
 from typing import Sequence
@@ -24,6 +27,11 @@ if not os.path.exists(LIB_PATH):
 import torch  # noqa: E402,F401
 
 _lib = ctypes.CDLL(LIB_PATH)
+
+# Destructors that run while the interpreter exits skip the C calls: the
+# process frees everything then, and the HIP runtime may already be gone.
+_EXITING = [False]
+atexit.register(lambda: _EXITING.__setitem__(0, True))
 
 __all__ = [
     "FHT_U8", "FHT_F32", "FHT_F64", "FHT_SPLIT_S", "FHT_SPLIT_T", "FHT_HDR_INTS", "QUADRANTS",
@@ -441,6 +449,15 @@ def _stream_handle(stream) -> int:
     return s.cuda_stream
 
 
+def _on(stream):
+    """Context for the tensors a call allocates: on the stream its kernels run
+    on, so the caching allocator never hands their memory to other work
+    while those kernels may still use it."""
+    if stream is None:
+        return contextlib.nullcontext()
+    return _torch().cuda.stream(stream)
+
+
 class Plan:
     """A plan for rows x cols images (owns the C plan)."""
 
@@ -480,11 +497,11 @@ class Plan:
                        for q in self.quadrants}
         self.offsets = {q: fht_plan_out_offset(self.handle, q) for q in self.quadrants}
 
-    def __del__(self):
+    def __del__(self, _exiting=_EXITING, _destroy=_lib.fht_plan_destroy):
         h = getattr(self, "handle", None)
-        if h:
-            fht_plan_destroy(h)
-            self.handle = None
+        if h and not _exiting[0]:
+            _destroy(h)
+        self.handle = None
 
     def new_out(self, device=None):
         torch = _torch()
@@ -511,10 +528,11 @@ class Plan:
 
     def forward(self, img, out=None, ws=None, stream=None) -> list:
         self.check_image(img)
-        if out is None:
-            out = self.new_out(img.device)
-        if ws is None and self.ws_bytes:
-            ws = self.new_ws(img.device)
+        with _on(stream):
+            if out is None:
+                out = self.new_out(img.device)
+            if ws is None and self.ws_bytes:
+                ws = self.new_ws(img.device)
         if out.numel() < self.out_elems or out.dtype != self.out_dtype or not out.is_contiguous():
             raise ValueError("output buffer has the wrong size or dtype")
         if self.ws_bytes and ws.numel() * ws.element_size() < self.ws_bytes:
@@ -532,11 +550,12 @@ class Plan:
                 or gout.numel() < self.out_elems:
             raise ValueError("output gradient must be a contiguous device tensor of the "
                              "plan's output size and dtype")
-        if gimg is None:
-            gimg = torch.empty((self.rows, self.cols), dtype=self.in_dtype, device=gout.device)
         abytes = fht_plan_adjoint_workspace_bytes(self.handle)
-        if ws is None and abytes:
-            ws = torch.empty(abytes, dtype=torch.uint8, device=gout.device)
+        with _on(stream):
+            if gimg is None:
+                gimg = torch.empty((self.rows, self.cols), dtype=self.in_dtype, device=gout.device)
+            if ws is None and abytes:
+                ws = torch.empty(abytes, dtype=torch.uint8, device=gout.device)
         fht_adjoint(self.handle, gout.data_ptr(), gimg.data_ptr(),
                     ws.data_ptr() if ws is not None else None, _stream_handle(stream))
         return gimg
@@ -551,13 +570,14 @@ class Plan:
             raise ValueError(f"images must be contiguous {self.in_dtype} of shape "
                              f"(n, {self.rows}, {self.cols}) on the device")
         n = imgs.shape[0]
-        if outs is None:
-            outs = torch.empty((n, self.out_elems), dtype=self.out_dtype, device=imgs.device)
+        wbytes = fht_plan_workspace_bytes_many(self.handle, n)
+        with _on(stream):
+            if outs is None:
+                outs = torch.empty((n, self.out_elems), dtype=self.out_dtype, device=imgs.device)
+            if ws is None and wbytes:
+                ws = torch.empty(wbytes, dtype=torch.uint8, device=imgs.device)
         if outs.shape != (n, self.out_elems) or outs.dtype != self.out_dtype or not outs.is_contiguous():
             raise ValueError("outputs must be a contiguous (n, out_elems) tensor of the output dtype")
-        wbytes = fht_plan_workspace_bytes_many(self.handle, n)
-        if ws is None and wbytes:
-            ws = torch.empty(wbytes, dtype=torch.uint8, device=imgs.device)
         fht_forward_many(self.handle, n, imgs.data_ptr(), imgs.stride(0) * imgs.element_size(),
                          outs.data_ptr(), outs.stride(0) * outs.element_size(),
                          ws.data_ptr() if ws is not None else None, _stream_handle(stream))
@@ -571,11 +591,13 @@ class Plan:
                 or gouts.shape[1] != self.out_elems or gouts.dtype != self.out_dtype:
             raise ValueError("output gradients must be a contiguous (n, out_elems) device tensor")
         n = gouts.shape[0]
-        if gimgs is None:
-            gimgs = torch.empty((n, self.rows, self.cols), dtype=self.in_dtype, device=gouts.device)
         wbytes = fht_plan_adjoint_workspace_bytes_many(self.handle, n)
-        if ws is None and wbytes:
-            ws = torch.empty(wbytes, dtype=torch.uint8, device=gouts.device)
+        with _on(stream):
+            if gimgs is None:
+                gimgs = torch.empty((n, self.rows, self.cols), dtype=self.in_dtype,
+                                    device=gouts.device)
+            if ws is None and wbytes:
+                ws = torch.empty(wbytes, dtype=torch.uint8, device=gouts.device)
         fht_adjoint_many(self.handle, n, gouts.data_ptr(), gouts.stride(0) * gouts.element_size(),
                          gimgs.data_ptr(), gimgs.stride(0) * gimgs.element_size(),
                          ws.data_ptr() if ws is not None else None, _stream_handle(stream))
@@ -589,9 +611,11 @@ class Plan:
         torch = _torch()
         if not out.is_cuda or not out.is_contiguous() or out.numel() < self.out_elems:
             raise ValueError("output must be a contiguous device tensor of the plan's size")
-        ws = torch.empty(fht_peaks_workspace_bytes(capacity), dtype=torch.uint8, device=out.device)
-        rec = torch.zeros(k * PEAK_DTYPE.itemsize, dtype=torch.uint8, device=out.device)
-        found = torch.zeros(2, dtype=torch.int32, device=out.device)
+        with _on(stream):
+            ws = torch.empty(fht_peaks_workspace_bytes(capacity), dtype=torch.uint8,
+                             device=out.device)
+            rec = torch.zeros(k * PEAK_DTYPE.itemsize, dtype=torch.uint8, device=out.device)
+            found = torch.zeros(2, dtype=torch.int32, device=out.device)
         fht_peaks(self.handle, out.data_ptr(), k, radius, float(min_value), capacity, ws.data_ptr(),
                   rec.data_ptr(), found.data_ptr(), _stream_handle(stream))
         if stream is not None:
@@ -629,11 +653,7 @@ def hough_autograd(img, split="S", quadrants=(0, 1, 2, 3)) -> list:
     (n x rows x cols): one tensor per quadrant, (W, H) or (n, W, H), views of
     one flat output whose backward runs the library's adjoint."""
     shape = tuple(img.shape[-2:])
-    key = (shape, img.dtype, _split_code(split), tuple(quadrants))
-    plan = _plan_cache.get(key)
-    if plan is None:
-        plan = Plan(shape[0], shape[1], img.dtype, split, quadrants)
-        _plan_cache[key] = plan
+    plan = _cached_plan(shape, img.dtype, split, quadrants)
     out = HoughFunction.apply(img, plan)
     if img.dim() == 2:
         return plan.split_out(out)
@@ -710,11 +730,11 @@ class Batch:
             self.staging = staging
         self.tables = tables
 
-    def __del__(self):
+    def __del__(self, _exiting=_EXITING, _destroy=_lib.fht_batch_destroy):
         h = getattr(self, "handle", None)
-        if h:
-            fht_batch_destroy(h)
-            self.handle = None
+        if h and not _exiting[0]:
+            _destroy(h)
+        self.handle = None
 
     def new_ws(self, device=None):
         torch = _torch()
@@ -747,14 +767,25 @@ class Batch:
         return graph
 
 
-_plan_cache: dict = {}
+# Plans of `hough` and `hough_autograd`, least recently used first.  A plan
+# dropped from here lives on while a tensor's autograd graph still holds it.
+PLAN_CACHE_SIZE = 64
+_plan_cache: "collections.OrderedDict" = collections.OrderedDict()
+
+
+def _cached_plan(shape, dtype, split, quadrants) -> Plan:
+    key = (tuple(shape), dtype, _split_code(split), tuple(sorted(set(quadrants))))
+    plan = _plan_cache.get(key)
+    if plan is None:
+        plan = Plan(shape[0], shape[1], dtype, split, quadrants)
+        _plan_cache[key] = plan
+        while len(_plan_cache) > PLAN_CACHE_SIZE:
+            _plan_cache.popitem(last=False)
+    else:
+        _plan_cache.move_to_end(key)
+    return plan
 
 
 def hough(img, split="S", quadrants=(0, 1, 2, 3)) -> list:
     """Transform one device image; returns one (W, H) tensor per quadrant."""
-    key = (tuple(img.shape), img.dtype, _split_code(split), tuple(quadrants))
-    plan = _plan_cache.get(key)
-    if plan is None:
-        plan = Plan(img.shape[0], img.shape[1], img.dtype, split, quadrants)
-        _plan_cache[key] = plan
-    return plan.forward(img)
+    return _cached_plan(img.shape, img.dtype, split, quadrants).forward(img)

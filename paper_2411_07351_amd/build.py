@@ -8,6 +8,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -55,9 +56,11 @@ def _run(cmd):
         sys.stderr.write(msg + "\n")
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compiles every source (in parallel, ``jobs`` at a time; 0: one per
+    source, at most 8) and links the library."""
     os.makedirs(OUT, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for name, kind in SOURCES:
         src = os.path.join(CSRC, name)
         obj = os.path.join(OUT, name + ".o")
@@ -67,8 +70,11 @@ def build(verbose: bool = False) -> str:
             cmd = [HIPCC] + HIP_FLAGS + ["-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd))
-        _run(cmd)
+        cmds.append(cmd)
         objs.append(obj)
+    with ThreadPoolExecutor(max_workers=jobs or min(8, len(cmds))) as pool:
+        for f in [pool.submit(_run, c) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     tdir = _torch_lib_dir()

@@ -1519,7 +1519,7 @@ fht_status fht_peaks(fht_plan plan, const void *d_out, int32_t k, int32_t radius
     fht::PeakArgs a;
     std::memset(&a, 0, sizeof(a));
     const size_t eb = acc_bytes(plan->dtype);
-    int max_elems = 0;
+    size_t max_elems = 0;
     for (int q = 0; q < 4; ++q) {
         if (!(plan->qmask & (1u << q))) continue;
         const int v = q >> 1;
@@ -1529,7 +1529,7 @@ fht_status fht_peaks(fht_plan plan, const void *d_out, int32_t k, int32_t radius
         a.H[j] = plan->vH[v];
         a.base[j] = plan->out_off[q];
         a.quadrant[j] = q;
-        max_elems = std::max(max_elems, plan->vW[v] * plan->vH[v]);
+        max_elems = std::max(max_elems, static_cast<size_t>(plan->vW[v]) * plan->vH[v]);
     }
     a.radius = radius;
     a.min_value = min_value;

@@ -125,14 +125,14 @@ struct PeakArgs {
     double min_value;
     int32_t k, capacity;
     uint32_t *counter;             // workspace: candidate count
-    uint64_t *keys;                // workspace: candidate keys (value bits << 32 | ~index)
+    uint64_t *keys;                // workspace: candidate keys (quadrant slot << 48 | index)
     PeakOut *out;                  // k peaks, strongest first
     int32_t *n_found;              // [0] peaks written, [1] candidates found
 };
 
 enum class PeakElem { I32, F32, F64 };
 
-hipError_t launch_peaks(PeakElem elem, const PeakArgs &args, int max_elems, hipStream_t stream);
+hipError_t launch_peaks(PeakElem elem, const PeakArgs &args, size_t max_elems, hipStream_t stream);
 
 hipError_t launch_adjoint_step(Real real, const AdjArgs &args, int n_jobs, int max_w,
                                hipStream_t stream, int n_images = 1);

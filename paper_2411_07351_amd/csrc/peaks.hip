@@ -11,16 +11,11 @@ namespace fht {
 
 namespace {
 
-__device__ __forceinline__ uint32_t order_bits(float v)
-{
-    const uint32_t u = __float_as_uint(v);
-    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-
-__device__ __forceinline__ float from_order_bits(uint32_t u)
-{
-    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
-}
+// A candidate's key is its quadrant slot (bits 48..) and its index in that
+// quadrant: quadrants are stored in q order, so keys order candidates by their
+// flat output index.
+constexpr uint64_t kNoKey = ~0ull;
+constexpr int kKeySlotShift = 48;
 
 __global__ void peaks_clear_kernel(uint32_t *counter) { if (threadIdx.x == 0) counter[0] = 0; }
 
@@ -53,51 +48,87 @@ __global__ void __launch_bounds__(256) peaks_nms_kernel(PeakArgs a)
         }
     }
     const uint32_t slot = atomicAdd(a.counter, 1u);
-    if (slot < static_cast<uint32_t>(a.capacity)) {
-        const uint64_t idx = a.base[qi] + e;
-        a.keys[slot] = (static_cast<uint64_t>(order_bits(static_cast<float>(v))) << 32) |
-                       (0xffffffffull - idx);
-    }
+    if (slot < static_cast<uint32_t>(a.capacity))
+        a.keys[slot] = (static_cast<uint64_t>(qi) << kKeySlotShift) | e;
+}
+
+template <typename T>
+__device__ __forceinline__ double key_value(const PeakArgs &a, uint64_t key)
+{
+    const int qi = static_cast<int>(key >> kKeySlotShift);
+    const size_t e = key & ((1ull << kKeySlotShift) - 1);
+    const void *src = qi == 0 ? a.src[0] : qi == 1 ? a.src[1] : qi == 2 ? a.src[2] : a.src[3];
+    return static_cast<double>(static_cast<const T *>(src)[e]);
+}
+
+// (value, key) beats (bv, bk): larger value, then smaller flat index.  Every
+// output type converts to double exactly, so the order is the values' own.
+__device__ __forceinline__ bool beats(double v, uint64_t k, double bv, uint64_t bk)
+{
+    return bk == kNoKey || v > bv || (v == bv && k < bk);
 }
 
 constexpr int kSelThreads = 1024;
 
-// The k largest keys (value, then smaller output index) by k rounds of a
-// workgroup argmax; each round removes its winner.
+// The k strongest candidates (value descending, then flat output index
+// ascending) by k rounds of a workgroup argmax; each round removes its
+// winner.
+template <typename T>
 __global__ void __launch_bounds__(kSelThreads) peaks_select_kernel(PeakArgs a)
 {
-    __shared__ uint64_t best[kSelThreads / 64];
+    __shared__ double best_v[kSelThreads / 64];
+    __shared__ uint64_t best_k[kSelThreads / 64];
     const uint32_t total = a.counter[0];
     const int m = static_cast<int>(min(total, static_cast<uint32_t>(a.capacity)));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int found = 0;
     for (int round = 0; round < a.k; ++round) {
-        uint64_t mine = 0;
-        for (int i = threadIdx.x; i < m; i += kSelThreads) mine = max(mine, a.keys[i]);
-        for (int off = 32; off > 0; off >>= 1) {
-            const uint64_t o = __shfl_xor(mine, off, 64);
-            mine = max(mine, o);
+        double bv = 0.0;
+        uint64_t bk = kNoKey;
+        for (int i = threadIdx.x; i < m; i += kSelThreads) {
+            const uint64_t k = a.keys[i];
+            if (k == kNoKey) continue;
+            const double v = key_value<T>(a, k);
+            if (beats(v, k, bv, bk)) {
+                bv = v;
+                bk = k;
+            }
         }
-        if (lane == 0) best[wave] = mine;
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(bv, off, 64);
+            const uint64_t ok = __shfl_xor(bk, off, 64);
+            if (ok != kNoKey && beats(ov, ok, bv, bk)) {
+                bv = ov;
+                bk = ok;
+            }
+        }
+        if (lane == 0) {
+            best_v[wave] = bv;
+            best_k[wave] = bk;
+        }
         __syncthreads();
-        uint64_t top = 0;
-        for (int w = 0; w < kSelThreads / 64; ++w) top = max(top, best[w]);
+        double tv = 0.0;
+        uint64_t tk = kNoKey;
+        for (int w = 0; w < kSelThreads / 64; ++w)
+            if (best_k[w] != kNoKey && beats(best_v[w], best_k[w], tv, tk)) {
+                tv = best_v[w];
+                tk = best_k[w];
+            }
         __syncthreads();
-        if (top == 0) break;
+        if (tk == kNoKey) break;
         // remove the winner (keys are unique: they hold the output index)
         for (int i = threadIdx.x; i < m; i += kSelThreads)
-            if (a.keys[i] == top) a.keys[i] = 0;
+            if (a.keys[i] == tk) a.keys[i] = kNoKey;
         if (threadIdx.x == 0) {
-            const uint64_t idx = 0xffffffffull - (top & 0xffffffffull);
-            int q = 0;
-            for (int j = 1; j < a.nq; ++j)
-                if (idx >= a.base[j]) q = j;
-            const uint64_t rel = idx - a.base[q];
+            const int qi = static_cast<int>(tk >> kKeySlotShift);
+            const uint64_t e = tk & ((1ull << kKeySlotShift) - 1);
+            const int H = qi == 0 ? a.H[0] : qi == 1 ? a.H[1] : qi == 2 ? a.H[2] : a.H[3];
             PeakOut p;
-            p.value = from_order_bits(static_cast<uint32_t>(top >> 32));
-            p.quadrant = a.quadrant[q];
-            p.t = static_cast<int32_t>(rel / a.H[q]);
-            p.s = static_cast<int32_t>(rel % a.H[q]);
+            p.value = static_cast<float>(tv);
+            p.quadrant = qi == 0 ? a.quadrant[0] : qi == 1 ? a.quadrant[1]
+                       : qi == 2 ? a.quadrant[2] : a.quadrant[3];
+            p.t = static_cast<int32_t>(e / H);
+            p.s = static_cast<int32_t>(e % H);
             a.out[round] = p;
         }
         ++found;
@@ -111,18 +142,25 @@ __global__ void __launch_bounds__(kSelThreads) peaks_select_kernel(PeakArgs a)
 
 }  // namespace
 
-hipError_t launch_peaks(PeakElem elem, const PeakArgs &args, int max_elems, hipStream_t stream)
+hipError_t launch_peaks(PeakElem elem, const PeakArgs &args, size_t max_elems, hipStream_t stream)
 {
+    if (max_elems > (static_cast<size_t>(0x7fffffff) * 256)) return hipErrorInvalidValue;
     peaks_clear_kernel<<<1, 64, 0, stream>>>(args.counter);
-    if (max_elems > 0) {
-        const dim3 grid((max_elems + 255) / 256, args.nq), block(256);
-        switch (elem) {
-        case PeakElem::I32: peaks_nms_kernel<int32_t><<<grid, block, 0, stream>>>(args); break;
-        case PeakElem::F32: peaks_nms_kernel<float><<<grid, block, 0, stream>>>(args); break;
-        case PeakElem::F64: peaks_nms_kernel<double><<<grid, block, 0, stream>>>(args); break;
-        }
+    const dim3 grid(static_cast<unsigned>((max_elems + 255) / 256), args.nq), block(256);
+    switch (elem) {
+    case PeakElem::I32:
+        if (max_elems > 0) peaks_nms_kernel<int32_t><<<grid, block, 0, stream>>>(args);
+        peaks_select_kernel<int32_t><<<1, kSelThreads, 0, stream>>>(args);
+        break;
+    case PeakElem::F32:
+        if (max_elems > 0) peaks_nms_kernel<float><<<grid, block, 0, stream>>>(args);
+        peaks_select_kernel<float><<<1, kSelThreads, 0, stream>>>(args);
+        break;
+    case PeakElem::F64:
+        if (max_elems > 0) peaks_nms_kernel<double><<<grid, block, 0, stream>>>(args);
+        peaks_select_kernel<double><<<1, kSelThreads, 0, stream>>>(args);
+        break;
     }
-    peaks_select_kernel<<<1, kSelThreads, 0, stream>>>(args);
     return hipGetLastError();
 }
 

@@ -8,7 +8,8 @@ SIGMA = {0: 1, 1: -1, 2: 1, 3: -1}
 def local_maxima_topk(outs: dict, k: int, radius: int, min_value: float):
     """fht_peaks' definition: strict (2r+1)^2 maxima per quadrant (s wraps,
     t clipped; an equal neighbour earlier in the quadrant's row-major order
-    wins), value >= min_value, the k largest by (value desc, flat index asc).
+    wins), value >= min_value, the k largest by (value desc, flat index asc),
+    ordered by the exact values and reported as float32.
     `outs` maps quadrant -> (array W x H, flat offset of its first element)."""
     cands = []
     for q, (J, base) in outs.items():
@@ -36,9 +37,9 @@ def local_maxima_topk(outs: dict, k: int, radius: int, min_value: float):
                     if not ok:
                         break
                 if ok:
-                    cands.append((float(np.float32(v)), base + e, q, t, s))
+                    cands.append((float(v), base + e, q, t, s))
     cands.sort(key=lambda c: (-c[0], c[1]))
-    return [(v, q, t, s) for v, _, q, t, s in cands[:k]], len(cands)
+    return [(float(np.float32(v)), q, t, s) for v, _, q, t, s in cands[:k]], len(cands)
 
 
 def segment_lines(r0, c0, r1, c1, R, C):

@@ -91,6 +91,17 @@ def test_bench_ragged_512_graph_every_image():
     srng = np.random.default_rng(18)
     for p, o, img in zip(plans, outs, imgs_np):
         _check_u8(p, o, img, 0, srng, 40)
+    # every output of every image: equal to plain per-image launches, and
+    # every slope row of every quadrant sums to the image sum (each line
+    # family partitions the pixels, Sec. 3)
+    for p, o, img in zip(plans, outs, imgs):
+        solo = p.new_out("cuda")
+        p.forward(img, solo)
+        assert torch.equal(solo, o), (img.shape,)
+        total = int(img.sum())
+        for g in p.split_out(o):
+            assert (g.sum(dim=1, dtype=torch.int64) == total).all(), (img.shape,)
+    torch.cuda.synchronize()
     # the smallest images in full
     order = sorted(range(512), key=lambda i: shapes[i][0] * shapes[i][1])[:20]
     for i in order:

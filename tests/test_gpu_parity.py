@@ -228,6 +228,51 @@ def test_forward_many_equals_single_images(F, kind, shape, n):
         assert torch.equal(outs[b], solo), b
 
 
+def test_forward_many_config4_f32_vs_oracle(F):
+    # the batch the differentiable leg times: 32 float32 384 x 257 images in
+    # one launch per pass, every image against the oracle
+    n, R, C = 32, 384, 257
+    rng = WL.rng_for(4)
+    imgs_np = np.stack([WL.normal_f32(rng, R, C) for _ in range(n)])
+    plan = F.Plan(R, C, "f32", "S")
+    outs = plan.forward_many(torch.from_numpy(imgs_np).cuda())
+    torch.cuda.synchronize()
+    outs = outs.cpu().numpy()
+    for b in range(n):
+        ref, ab = native.hough4_f64(imgs_np[b].astype(np.float64), 0)
+        for q, (W, H) in plan.shapes.items():
+            off = plan.offsets[q]
+            _assert_float_close(outs[b, off:off + W * H].reshape(W, H), ref[q], ab[q])
+
+
+def test_forward_on_a_side_stream_vs_oracle(F):
+    # Kernels enqueued on a caller's stream while the current stream allocates
+    # and frees memory: the call's own workspace and output must not be
+    # handed to that other work (they are allocated on the side stream).
+    rng = WL.rng_for(2, salt=50)
+    imgs_np = [WL.uniform_u8(rng, 700, 513), WL.normal_f32(rng, 300, 611)]
+    side = torch.cuda.Stream()
+    results = []
+    for img_np in imgs_np:
+        plan = F.Plan(img_np.shape[0], img_np.shape[1], "u8" if img_np.dtype == np.uint8 else "f32",
+                      "S")
+        img = torch.from_numpy(img_np).cuda()
+        side.wait_stream(torch.cuda.current_stream())
+        quads = plan.forward(img, stream=side)
+        for _ in range(20):  # allocation-heavy work on the current stream
+            junk = torch.full((1 << 22,), 3, dtype=torch.int32, device="cuda")
+            junk.add_(1)
+            del junk
+        torch.cuda.current_stream().wait_stream(side)
+        results.append([g.cpu().numpy() for g in quads])
+    ref = native.hough4_u8(imgs_np[0], 0)
+    for q in range(4):
+        assert (results[0][q] == ref[q]).all(), q
+    ref, ab = native.hough4_f64(imgs_np[1].astype(np.float64), 0)
+    for q in range(4):
+        _assert_float_close(results[1][q], ref[q], ab[q])
+
+
 @pytest.mark.parametrize("kind", ["u8", "f32", "f64"])
 def test_random_shapes_every_path(F, kind):
     # Seeded shapes, log-uniform per side up to 1100 lanes, plus shapes whose

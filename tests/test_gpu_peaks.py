@@ -37,6 +37,26 @@ def test_peaks_equal_reference(case):
     assert _as_list(recs) == ref
 
 
+def test_peaks_f64_order_by_exact_value():
+    # float64 outputs that round to the same float32 must still be ordered by
+    # their own values: integer pixels plus a perturbation far below float32
+    # resolution at these magnitudes
+    rng = WL.rng_for(1, salt=30)
+    R, C = 40, 36
+    img = np.round(rng.standard_normal((R, C)) * 3.0) + 1e-9 * rng.standard_normal((R, C))
+    plan = F.Plan(R, C, "f64", "S")
+    out = plan.new_out("cuda")
+    plan.forward(torch.from_numpy(img).cuda(), out)
+    recs, cands = plan.peaks(out, k=60, radius=1, min_value=-1e30)
+    flat = out.cpu().numpy()
+    ref, ref_cands = local_maxima_topk(_outs(plan, flat), 60, 1, -1e30)
+    assert cands == ref_cands
+    assert _as_list(recs) == ref
+    # and some neighbours in that order are equal as float32 but not as float64
+    vals = [flat[plan.offsets[q] + t * plan.shapes[q][1] + s] for _, q, t, s in ref]
+    assert any(a != b and np.float32(a) == np.float32(b) for a, b in zip(vals, vals[1:]))
+
+
 def test_peaks_recover_planted_segments():
     R = C = 1021
     img, ends = WL.edge_map_segments(WL.rng_for(2), R, C)

@@ -1,10 +1,11 @@
 """The serving loop on the GPU: results in the mix equal results alone.
 
 Requests of mixed sizes and dtypes arrive as a Poisson stream fast enough
-that batches overlap on two streams; every request's four Hough images must
-equal those of the same image transformed alone (``Plan.forward``, itself
-checked against the oracle by the parity tests): bit for bit, for uint8 and
-float32 alike, since both paths run the same programs.
+that batches overlap on two streams.  Every request's four Hough images must
+equal the C oracle's (uint8 bit-exact, float32 within 1e-5 of each line's
+absolute sum), and equal those of the same image transformed alone
+(``Plan.forward``) bit for bit, for uint8 and float32 alike, since both paths
+run the same programs.
 """
 import numpy as np
 import pytest
@@ -13,6 +14,7 @@ import torch
 import paper_2411_07351_amd as F
 from paper_2411_07351_amd import serving as S
 import workloads as WL
+from oracle import native
 
 pytestmark = pytest.mark.gpu
 
@@ -25,9 +27,26 @@ def _requests(n, seed, qps, lo=64, hi=700):
             for i, ((kind, img), t) in enumerate(zip(items, arr))]
 
 
+def _check_oracle(r):
+    """The served result of request r against the C oracle (Sec. 3 sums)."""
+    img = r.image.numpy()
+    got = [g.cpu().numpy() for g in r.result()]
+    what = f"request {r.rid} ({r.rows}x{r.cols} {r.kind})"
+    if r.kind == "u8":
+        ref = native.hough4_u8(img, 0)
+        for q in range(4):
+            assert got[q].dtype == np.int32 and (got[q] == ref[q]).all(), f"{what} quadrant {q}"
+    else:
+        ref, ab = native.hough4_f64(img.astype(np.float64), 0)
+        for q in range(4):
+            err = np.abs(got[q].astype(np.float64) - ref[q])
+            assert (err <= 1e-5 * ab[q] + 1e-30).all(), f"{what} quadrant {q}"
+
+
 def _check_solo(reqs):
     for r in reqs:
         assert r.status == "done", (r.rid, r.status, r.error)
+        _check_oracle(r)
         img = r.image.cuda()
         solo = F.Plan(r.rows, r.cols, r.kind, "S").forward(img)
         torch.cuda.synchronize()

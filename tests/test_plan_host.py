@@ -47,7 +47,7 @@ def test_tables_large_widths_sampled(split):
     # outputs of the interpreter with the C oracle.
     from oracle import native
     rng = np.random.default_rng(22)
-    for R, C in ((300, 9), (9, 257), (1021, 5)):
+    for R, C in ((300, 9), (9, 257), (1021, 5), (8191, 3)):
         img = rng.integers(0, 256, size=(R, C), dtype=np.uint8)
         h = F.fht_plan_create(R, C, F.FHT_U8, split, 15, None)
         try:
