@@ -30,6 +30,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, vendor figure
 METRIC = "input Mpixel/s + achieved HBM GB/s (batched vs plain); p50/p99 latency at fixed QPS"
 COMPULSORY_BPP = 17  # read a uint8 pixel once, write four int32 outputs once
+COMPULSORY_BPP_F32_FWD_ADJ = 40  # forward 4 + 16, adjoint 16 + 4 bytes per float32 pixel
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pass_kernels_1021x1021_u8.txt")
 
 
@@ -51,6 +52,8 @@ def _parse():
                     help="requests per serving run (0: skip the serving leg)")
     ap.add_argument("--serve-qps", type=float, default=200.0,
                     help="the fixed absolute request rate of the serving leg")
+    ap.add_argument("--ceilings", type=int, default=1,
+                    help="also measure torch's fill/copy/sum rates (1) or not (0)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -64,9 +67,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel: str):
+def _traffic(kernel: str, batched: bool = False):
     """HBM bytes per launch of `kernel` from the committed counter summary, if it
-    was taken on the current kernel sources (else None)."""
+    was taken on the current kernel sources (else None); `batched`: per launch
+    of the 64-image batch."""
     try:
         vals = {}
         with open(TRAFFIC_FILE) as fh:
@@ -79,8 +83,20 @@ def _traffic(kernel: str):
         return None
     if vals.get("kernel_source_hash") != kernel_source_hash():
         return None
-    v = vals.get(f"bytes_per_launch[{kernel}]")
+    key = "batched_bytes_per_launch" if batched else "bytes_per_launch"
+    v = vals.get(f"{key}[{kernel}]")
     return float(v) if v is not None else None
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _cpu_baseline(imgs_np, split: int, budget_s: float):
@@ -96,7 +112,90 @@ def _cpu_baseline(imgs_np, split: int, budget_s: float):
     return {"value": round(done * R * C / dt / 1e6, 3), "unit": "Mpixel/s",
             "cores": native.num_threads(), "kind": "oracle",
             "sample": f"{done} of {len(imgs_np)} images {R}x{C}, 4 quadrants, direct sums along "
-                      f"the generating patterns (C, OpenMP), {dt:.1f} s"}
+                      f"the generating patterns (C, OpenMP), {dt:.1f} s",
+            "cpu_model": cpu_model()}
+
+
+def _cpu_alg1(imgs_np, split: int, budget_s: float):
+    """Alg. 1's own recursion in C (O(W H log W) per quadrant, OpenMP over
+    images and quadrants): the like-for-like CPU counterpart of the GPU path,
+    over all the images, repeated while the budget lasts."""
+    from oracle import native
+    native.alg1_u8_batch(imgs_np[:2], split)  # warm: pages, threads
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        native.alg1_u8_batch(imgs_np, split)
+        reps += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    n, R, C = imgs_np.shape
+    return {"value": round(reps * n * R * C / dt / 1e6, 1), "unit": "Mpixel/s",
+            "cores": native.num_threads(), "kind": "alg1_recursion",
+            "sample": f"{reps} x {n} images {R}x{C}, 4 quadrants, int32, {dt:.1f} s",
+            "cpu_model": cpu_model()}
+
+
+def _latency_config1(torch, F, WL, reps: int = 400):
+    """One 61 x 47 uint8 image (the smallest workload): latency of single
+    transforms, each launched alone and waited for."""
+    img = torch.from_numpy(WL.uniform_u8(WL.rng_for(1), 61, 47)).cuda()
+    plan = F.Plan(61, 47, "u8", "S")
+    out = plan.new_out("cuda")
+    ws = plan.new_ws("cuda")
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+    for _ in range(20):
+        F.fht_forward(plan.handle, img.data_ptr(), out.data_ptr(), ws.data_ptr(), sh)
+    torch.cuda.synchronize()
+    gpu, host = [], []
+    for _ in range(reps):
+        a, b = _events(torch)
+        t0 = time.perf_counter()
+        a.record(stream)
+        F.fht_forward(plan.handle, img.data_ptr(), out.data_ptr(), ws.data_ptr(), sh)
+        b.record(stream)
+        b.synchronize()
+        host.append((time.perf_counter() - t0) * 1e3)
+        gpu.append(a.elapsed_time(b))
+    import numpy as np
+    pct = lambda v, p: round(float(np.percentile(v, p)), 4)
+    return {"workload": "one 61x47 uint8 image, 4 quadrants, FHT2DS, int32 outputs, "
+                        f"{F.fht_plan_num_launches(plan.handle)} launches, each transform "
+                        "launched alone and waited for",
+            "reps": reps,
+            "gpu_ms": {"p50": pct(gpu, 50), "p99": pct(gpu, 99)},
+            "host_ms": {"p50": pct(host, 50), "p99": pct(host, 99)}}
+
+
+def _ceilings(torch, mib: int = 2048):
+    """Practical HBM rates on this part: torch's fill (write only), copy and
+    sum (read only) over buffers much larger than the 256 MB memory-side
+    cache, timed with events."""
+    n = mib << 20
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    x = a.view(torch.float32)
+    stream = torch.cuda.current_stream()
+
+    def rate(fn, nbytes):
+        for _ in range(2):
+            fn()
+        e0, e1 = _events(torch)
+        e0.record(stream)
+        for _ in range(5):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return round(nbytes * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+
+    res = {"write_gbps": rate(lambda: a.fill_(1), n),
+           "copy_gbps": rate(lambda: b.copy_(a), 2 * n),
+           "read_gbps": rate(lambda: x.sum(), n),
+           "buffer_mib": mib, "how": "torch fill_, copy_, sum over uint8/float32 buffers"}
+    del a, b, x
+    torch.cuda.empty_cache()
+    return res
 
 
 def _serving(args, torch, F, WL):
@@ -214,9 +313,22 @@ def _differentiable(args, torch, F, WL):
     mf_ms, mb_ms = timed(fwd_many), timed(bwd_many)
     mfb_ms = timed(lambda: (fwd_many(), bwd_many()))
     px = n * R * C
+    fbytes = n * sum(sum(F.fht_plan_launch_info(plan.handle, l)[k] for k in ("bytes_in", "bytes_out"))
+                     for l in range(F.fht_plan_num_launches(plan.handle)))
+    comp = COMPULSORY_BPP_F32_FWD_ADJ * px
     return {"workload": f"{n} float32 {R}x{C} N(0,1) images, forward + adjoint, 4 quadrants, "
                         "one launch per pass or level for the whole batch",
             "value": round(px / (mfb_ms * 1e-3) / 1e6, 1), "unit": "Mpixel/s",
+            "roofline": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBPS,
+                         "compulsory_bytes": comp,
+                         "achieved_compulsory": round(comp / (mfb_ms * 1e-3) / 1e9, 1),
+                         "frac_compulsory": round(comp / (mfb_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                         "forward_bytes_scheduled": fbytes,
+                         "forward_gbps_scheduled": round(fbytes / (mf_ms * 1e-3) / 1e9, 1),
+                         "working_set_mb": round((px * 4 + 2 * n * plan.out_elems * 4 +
+                                                  mws.numel() + maws.numel()) / 1e6, 1),
+                         "note": "the working set fits the 256 MB memory-side cache, so these "
+                                 "rates are not HBM-only"},
             "forward_ms": round(mf_ms, 4), "adjoint_ms": round(mb_ms, 4),
             "forward_adjoint_ms": round(mfb_ms, 4),
             "per_image": {"value": round(px / (fb_ms * 1e-3) / 1e6, 1), "unit": "Mpixel/s",
@@ -328,6 +440,10 @@ def main():
             "launches_per_image": nl,
         },
         "effective_gbps": round(COMPULSORY_BPP * px_per_step * args.steps / plain_s / 1e9, 1),
+        "frac_compulsory": round(COMPULSORY_BPP * px_per_step * args.steps / plain_s / 1e9 /
+                                 HBM_PEAK_GBPS, 4),
+        "bytes_per_px_scheduled": round(sum(i["bytes_in"] + i["bytes_out"] for i in info) /
+                                        (R * C), 2),
         "event_ms_per_step": round(plain_event_ms, 3),
         "roofline": {
             "bound": "hbm",
@@ -377,12 +493,21 @@ def main():
         "ms_per_step": round(bms, 4),
         "graph": True,
         "effective_gbps": round(COMPULSORY_BPP * px_per_step / (bms * 1e-3) / 1e9, 1),
+        "frac_compulsory": round(COMPULSORY_BPP * px_per_step / (bms * 1e-3) / 1e9 /
+                                 HBM_PEAK_GBPS, 4),
         "launch_ms": [round(m, 4) for m in per_ms],
         "launch_gbps": ([round(by / (m * 1e-3) / 1e9, 1) for by, m in zip(lbytes, per_ms)]
                         if len(per_ms) == len(lbytes) else None),
         "path_gbps": round(sum(lbytes) / (bms * 1e-3) / 1e9, 1),
         "path_frac": round(sum(lbytes) / (bms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
     }
+    traf = [_traffic(F.fht_plan_launch_kernel(plan.handle, l), batched=True) for l in range(nl)]
+    if all(t is not None for t in traf):
+        result["batched"]["launch_traffic_bytes"] = [round(t, 0) for t in traf]
+        result["batched"]["traffic_gbps"] = round(sum(traf) / (bms * 1e-3) / 1e9, 1)
+        result["batched"]["traffic_frac"] = round(sum(traf) / (bms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+    result["batched"]["working_set_mb"] = round((imgs.numel() + outs.numel() * 4 +
+                                                 bws.numel()) / 1e6, 1)
     del graph, batch, bws
 
     if args.ragged > 0:
@@ -451,8 +576,13 @@ def main():
         torch.cuda.synchronize()
         result["copy_calibration_bytes"] = 2 * (args.copy_mib << 20)
 
+    result["latency_61x47"] = _latency_config1(torch, F, WL)
+    if args.ceilings:
+        result["hbm_ceilings"] = _ceilings(torch)
+
     if args.cpu_seconds > 0:
         result["cpu_baseline"] = _cpu_baseline(imgs_np, split, args.cpu_seconds)
+        result["cpu_alg1"] = _cpu_alg1(imgs_np, split, args.cpu_seconds)
     print(json.dumps(result), flush=True)
 
 

@@ -91,18 +91,22 @@ typedef struct {
     int32_t threads_first;
 } fht_schedule;
 
-/* Human-readable name of a status code (static storage). */
-const char *fht_status_string(fht_status s);
+/* Human-readable name of a status code (an fht_status value; static storage,
+ * "unknown status" for any other value). */
+const char *fht_status_string(int32_t s);
 
 /*
- * Build a plan for rows x cols images of the given dtype and split rule
- * (Sec. 3, Alg. 1).  quadrant_mask bit q selects output q (1..15).  sched may
- * be NULL.  Host-only: needs no GPU.  On success *out owns the plan.
+ * Build a plan for rows x cols images of the given dtype (an fht_dtype value)
+ * and split rule (an fht_split value; Sec. 3, Alg. 1).  Enumerated arguments
+ * of this ABI are passed as int32_t, so any value a caller passes is checked
+ * rather than being outside its enumeration.  quadrant_mask bit q selects
+ * output q (1..15).  sched may be NULL.  Host-only: needs no GPU.  On success
+ * *out owns the plan.
  * Errors: FHT_EINVAL (rows or cols < 1 or > 65536, mask 0 or > 15, bad
  * schedule), FHT_EDTYPE, FHT_ENOMEM.
  */
-fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, fht_dtype dtype,
-                           fht_split split, uint32_t quadrant_mask, const fht_schedule *sched);
+fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, int32_t dtype,
+                           int32_t split, uint32_t quadrant_mask, const fht_schedule *sched);
 
 /* Frees host and device tables of a plan; NULL is ignored.  The caller
  * must make sure no enqueued work still uses the plan. */
@@ -192,8 +196,8 @@ fht_status fht_plan_upload_programs_many(const fht_plan *plans, int32_t n);
  * thread fails, so capture with thread-local mode or while no plan is made.
  */
 fht_status fht_planner_create(int32_t threads, int32_t device, fht_planner *out);
-fht_status fht_planner_submit(fht_planner planner, int32_t rows, int32_t cols, fht_dtype dtype,
-                              fht_split split, uint32_t quadrant_mask, const fht_schedule *sched,
+fht_status fht_planner_submit(fht_planner planner, int32_t rows, int32_t cols, int32_t dtype,
+                              int32_t split, uint32_t quadrant_mask, const fht_schedule *sched,
                               int64_t *ticket);
 int32_t fht_planner_poll(fht_planner planner, int64_t ticket, fht_plan *plan, fht_status *status);
 void fht_planner_destroy(fht_planner planner);
@@ -358,11 +362,11 @@ fht_status fht_peaks(fht_plan plan, const void *d_out, int32_t k, int32_t radius
  * enqueue device work (fht_forward, fht_forward_many, fht_forward_launch,
  * fht_adjoint, fht_adjoint_many, fht_peaks,
  * fht_batch_upload, fht_batch_upload_staged, fht_batch_run, fht_batch_run_launch) return
- * `code` after checking their
+ * `code` (an fht_status value) after checking their
  * arguments and before enqueuing anything.  count <= 0 or code == FHT_OK
  * disarms it.  Process-wide; safe to call from any thread.
  */
-void fht_debug_fail_next(fht_status code, int32_t count);
+void fht_debug_fail_next(int32_t code, int32_t count);
 
 /*
  * Host view of a plan's tables, for inspection and tests of the planner.

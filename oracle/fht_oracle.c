@@ -282,6 +282,80 @@ int orc_error_numerators(int nmax, int split, int64_t *num)
     return rc;
 }
 
+/*
+ * Alg. 1 itself, FHT2D(w, h, I, Split), for the uint8 -> int32 transform: the
+ * paper's recursion, O(W H log W) additions per quadrant.  It is the CPU
+ * counterpart of the GPU path for timing (the direct sums above are the
+ * definition; tests check this recursion against them first).
+ *
+ * orc_alg1_rec computes the Hough image of lanes [a, a + w) of the lane-major
+ * array A (W_all lanes of h positions) into rows [a, a + w) of dst, with tmp
+ * as scratch of the same shape: both halves go to tmp (each using dst as its
+ * own scratch), then row t of the result is row [t k0] of the left half plus
+ * row [t k1] of the right half rotated by sigma (t - [t k1]) positions,
+ * Rotate(v, r)[s] = v[(s + r) mod h].
+ */
+static void orc_alg1_rec(const uint8_t *A, int h, int a, int w, int split, int sigma,
+                         int32_t *dst, int32_t *tmp)
+{
+    if (w == 1) {
+        const uint8_t *lane = A + (size_t)a * h;
+        int32_t *row = dst + (size_t)a * h;
+        for (int s = 0; s < h; ++s) row[s] = lane[s];
+        return;
+    }
+    int w0 = orc_split_left(w, split), w1 = w - w0;
+    orc_alg1_rec(A, h, a, w0, split, sigma, tmp, dst);
+    orc_alg1_rec(A, h, a + w0, w1, split, sigma, tmp, dst);
+    for (int t = 0; t < w; ++t) {
+        int t0 = (int)orc_rhe((int64_t)t * (w0 - 1), w - 1);
+        int t1 = (int)orc_rhe((int64_t)t * (w1 - 1), w - 1);
+        int64_t r = ((int64_t)sigma * (t - t1)) % h;
+        if (r < 0) r += h;
+        const int32_t *L = tmp + (size_t)(a + t0) * h;
+        const int32_t *Rr = tmp + (size_t)(a + w0 + t1) * h;
+        int32_t *row = dst + (size_t)(a + t) * h;
+        int s = 0;
+        for (; s < h - r; ++s) row[s] = L[s] + Rr[s + r];
+        for (; s < h; ++s) row[s] = L[s] + Rr[s + r - h];
+    }
+}
+
+/*
+ * Alg. 1 over n images of R x C (row-major, back to back), all four
+ * quadrants; outs receives each image's four int32 Hough images in q order
+ * (4 R C int32 per image).  Images and quadrants are spread over the OpenMP
+ * threads, each running the recursion on its own.  Returns 0, -1 on bad
+ * arguments, -2 when out of memory.
+ */
+int orc_alg1_u8_batch(const uint8_t *imgs, int n, int R, int C, int split, int32_t *outs)
+{
+    if (!imgs || !outs || n < 0 || orc_bad_shape(R, C, split)) return -1;
+    int rc = 0;
+    const size_t px = (size_t)R * C;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t job = 0; job < (int64_t)n * 4; ++job) {
+        const int i = (int)(job / 4), q = (int)(job % 4);
+        int W, H, sigma;
+        orc_view_dims(q, R, C, &W, &H, &sigma);
+        const uint8_t *img = imgs + (size_t)i * px;
+        uint8_t *A = (uint8_t *)malloc(px);
+        int32_t *tmp = (int32_t *)malloc(px * sizeof(int32_t));
+        if (!A || !tmp) { free(A); free(tmp); rc = -2; continue; }
+        if (q < 2) {
+            memcpy(A, img, px);
+        } else {
+            for (int x = 0; x < W; ++x)
+                for (int y = 0; y < H; ++y) A[(size_t)x * H + y] = img[(size_t)y * C + x];
+        }
+        size_t off = (size_t)i * 4 * px + (q == 0 ? 0 : q == 1 ? px : q == 2 ? 2 * px : 3 * px);
+        orc_alg1_rec(A, H, 0, W, split, sigma, outs + off, tmp);
+        free(A);
+        free(tmp);
+    }
+    return rc;
+}
+
 /* Threads an OpenMP parallel region of this library uses. */
 int orc_num_threads(void)
 {

@@ -44,6 +44,7 @@ def _load():
         lib.orc_hough_sample_f64.argtypes = [p, i32, i32, i32, i64, p, p, p, p, p]
         lib.orc_error_numerators.argtypes = [i32, i32, p]
         lib.orc_num_threads.argtypes = []
+        lib.orc_alg1_u8_batch.argtypes = [p, i32, i32, i32, i32, p]
         _lib = lib
     return _lib
 
@@ -125,6 +126,19 @@ def error_numerators(nmax: int, split: int) -> np.ndarray:
     if _load().orc_error_numerators(nmax, split, _ptr(num)) != 0:
         raise ValueError("orc_error_numerators failed")
     return num
+
+
+def alg1_u8_batch(imgs: np.ndarray, split: int) -> np.ndarray:
+    """Alg. 1's recursion (C, OpenMP over images and quadrants) for n uint8
+    images of one shape: returns (n, 4 R C) int32, quadrants in q order."""
+    imgs = np.ascontiguousarray(imgs, dtype=np.uint8)
+    if imgs.ndim == 2:
+        imgs = imgs[None]
+    n, R, C = imgs.shape
+    out = np.empty((n, 4 * R * C), dtype=np.int32)
+    if _load().orc_alg1_u8_batch(_ptr(imgs), n, R, C, split, _ptr(out)) != 0:
+        raise ValueError("orc_alg1_u8_batch failed")
+    return out
 
 
 def num_threads() -> int:

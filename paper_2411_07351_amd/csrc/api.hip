@@ -891,7 +891,7 @@ fht_status batch_checks(const fht_plan *plans, int32_t n, const void *const *d_i
 
 extern "C" {
 
-const char *fht_status_string(fht_status s)
+const char *fht_status_string(int32_t s)
 {
     switch (s) {
     case FHT_OK: return "ok";
@@ -905,15 +905,17 @@ const char *fht_status_string(fht_status s)
     return "unknown status";
 }
 
-fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, fht_dtype dtype,
-                           fht_split split, uint32_t quadrant_mask, const fht_schedule *sched)
+fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, int32_t dtype_arg,
+                           int32_t split_arg, uint32_t quadrant_mask, const fht_schedule *sched)
 {
     if (!out) return FHT_EINVAL;
     *out = nullptr;
     if (rows < 1 || cols < 1 || rows > 65536 || cols > 65536) return FHT_EINVAL;
     if (quadrant_mask == 0 || quadrant_mask > 15) return FHT_EINVAL;
-    if (split != FHT_SPLIT_S && split != FHT_SPLIT_T) return FHT_EINVAL;
-    if (dtype != FHT_U8 && dtype != FHT_F32 && dtype != FHT_F64) return FHT_EDTYPE;
+    if (split_arg != FHT_SPLIT_S && split_arg != FHT_SPLIT_T) return FHT_EINVAL;
+    if (dtype_arg != FHT_U8 && dtype_arg != FHT_F32 && dtype_arg != FHT_F64) return FHT_EDTYPE;
+    const fht_dtype dtype = static_cast<fht_dtype>(dtype_arg);
+    const fht_split split = static_cast<fht_split>(split_arg);
     fht::Schedule sc;
     if (make_schedule(sched, &sc) != FHT_OK) return FHT_EINVAL;
 
@@ -1545,9 +1547,9 @@ fht_status fht_peaks(fht_plan plan, const void *d_out, int32_t k, int32_t radius
     return hip_status(fht::launch_peaks(elem, a, max_elems, static_cast<hipStream_t>(stream)));
 }
 
-void fht_debug_fail_next(fht_status code, int32_t count)
+void fht_debug_fail_next(int32_t code, int32_t count)
 {
-    g_fail_code.store(static_cast<int>(code));
+    g_fail_code.store(code);
     g_fail_count.store(count > 0 && code != FHT_OK ? count : 0);
 }
 

@@ -20,8 +20,8 @@ namespace {
 struct Task {
     int64_t ticket;
     int32_t rows, cols;
-    fht_dtype dtype;
-    fht_split split;
+    int32_t dtype;
+    int32_t split;
     uint32_t qmask;
     bool has_sched;
     fht_schedule sched;
@@ -147,8 +147,8 @@ fht_status fht_planner_create(int32_t threads, int32_t device, fht_planner *out)
     return FHT_OK;
 }
 
-fht_status fht_planner_submit(fht_planner pl, int32_t rows, int32_t cols, fht_dtype dtype,
-                              fht_split split, uint32_t quadrant_mask,
+fht_status fht_planner_submit(fht_planner pl, int32_t rows, int32_t cols, int32_t dtype,
+                              int32_t split, uint32_t quadrant_mask,
                               const fht_schedule *sched, int64_t *ticket)
 {
     if (!pl || !ticket) return FHT_EINVAL;

@@ -488,3 +488,28 @@ def test_sample_f64_pin_rejects_planted_mistakes(tmp_path, mistake):
                     str(lib_path), str(tmp_path / "bad.c")], check=True)
     bad = ctypes.CDLL(str(lib_path))
     assert not _sampler_matches_full_transform(lambda *a: _sample_f64_with(bad, *a))
+
+
+# ------------------------------------------------- Alg. 1 recursion in C
+
+@pytest.mark.parametrize("split", SPLITS)
+def test_c_alg1_recursion_equals_direct_sums(split):
+    """The C Alg. 1 recursion (the CPU timing baseline) gives the direct
+    pattern sums (Sec. 3: the recursion sums exactly along Alg. 2's patterns)
+    on every output, including W > H, W = 1, H = 1 and power-of-two sizes."""
+    rng = np.random.default_rng(43)
+    for R, C in ((1, 1), (1, 7), (7, 1), (2, 3), (13, 11), (5, 17), (61, 47), (32, 32),
+                 (33, 100), (129, 6)):
+        imgs = rng.integers(0, 256, size=(3, R, C), dtype=np.uint8)
+        got = native.alg1_u8_batch(imgs, split)
+        for i in range(3):
+            ref = native.hough4_u8(imgs[i], split)
+            assert (got[i] == np.concatenate([r.ravel() for r in ref])).all(), (R, C, i)
+    # and the Python statement of Alg. 1 on a small case
+    img = rng.integers(0, 256, size=(9, 6), dtype=np.uint8)
+    got = native.alg1_u8_batch(img, split)[0]
+    off = 0
+    for A, sigma in O.quadrant_views(img):
+        n = A.size
+        assert (got[off:off + n].reshape(A.shape) == O.fht2d(A, split, sigma)).all()
+        off += n
