@@ -213,6 +213,26 @@ void fht_planner_destroy(fht_planner planner);
 fht_status fht_forward(fht_plan plan, const void *d_img, void *d_out, void *d_ws, void *stream);
 
 /*
+ * fht_forward without allocating, for callers that cannot call hipMalloc:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * device allocation.  The workspace is the library's own static device
+ * scratch of FHT_NOALLOC_WS_BYTES bytes (64 MiB: 32 bytes per pixel covers
+ * about 2 Mpx, e.g. 1448 x 1448), one copy per device, held until the
+ * process ends.  The plan's tables must already be on the current device
+ * (fht_plan_upload, or an earlier fht_forward there); this call allocates
+ * nothing.  Every call on one device shares that device's scratch, so calls
+ * that overlap on one device (other streams, other threads) race and give
+ * wrong results; the scratch keeps the last call's contents, and since every
+ * element is written before it is read nothing needs clearing.
+ *   d_img, d_out, stream  as fht_forward
+ * Errors: FHT_EINVAL (null pointers, fht_plan_workspace_bytes(plan) above
+ * FHT_NOALLOC_WS_BYTES, tables not uploaded to the current device),
+ * FHT_ENODEV, FHT_EHIP.
+ */
+#define FHT_NOALLOC_WS_BYTES ((size_t)64 * 1024 * 1024)
+fht_status fht_forward_noalloc(fht_plan plan, const void *d_img, void *d_out, void *stream);
+
+/*
  * fht_forward for n same-shape images at once (one launch per fused pass for
  * all of them): image b is read at d_imgs + b * img_stride and its output
  * written at d_outs + b * out_stride (strides in bytes, >= 0, multiples of

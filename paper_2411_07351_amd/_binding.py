@@ -49,6 +49,7 @@ __all__ = [
     "fht_plan_adjoint_num_passes", "fht_plan_adjoint_pass", "fht_batch_upload_staged",
     "fht_plan_upload_programs", "fht_planner_create", "fht_planner_submit", "fht_planner_poll",
     "fht_planner_destroy", "fht_plan_upload_programs_many", "fht_batch_copy_images", "STATUS",
+    "fht_forward_noalloc", "NOALLOC_WS_BYTES",
 ]
 
 FHT_U8, FHT_F32, FHT_F64 = 0, 1, 2
@@ -72,8 +73,11 @@ EXPORTED = (
     "fht_adjoint_many", "fht_plan_adjoint_num_passes", "fht_plan_adjoint_pass",
     "fht_batch_upload_staged", "fht_plan_upload_programs",
     "fht_planner_create", "fht_planner_submit", "fht_planner_poll", "fht_planner_destroy",
-    "fht_plan_upload_programs_many", "fht_batch_copy_images",
+    "fht_plan_upload_programs_many", "fht_batch_copy_images", "fht_forward_noalloc",
 )
+
+# FHT_NOALLOC_WS_BYTES: the static scratch fht_forward_noalloc uses
+NOALLOC_WS_BYTES = 64 * 1024 * 1024
 
 # struct fht_peak
 PEAK_DTYPE = np.dtype([("value", np.float32), ("quadrant", np.int32), ("t", np.int32),
@@ -118,6 +122,7 @@ _sig("fht_plan_adjoint_workspace_bytes_many", _sz, _vp, _i32)
 _sig("fht_adjoint_many", _i32, _vp, _i32, _vp, _i64, _vp, _i64, _vp, _vp)
 _sig("fht_plan_upload", _i32, _vp)
 _sig("fht_forward", _i32, _vp, _vp, _vp, _vp, _vp)
+_sig("fht_forward_noalloc", _i32, _vp, _vp, _vp, _vp)
 _sig("fht_forward_launch", _i32, _vp, _i32, _vp, _vp, _vp, _vp)
 _sig("fht_batch_create", _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i32,
      ctypes.POINTER(_vp), ctypes.POINTER(_vp))
@@ -266,6 +271,10 @@ def fht_forward(plan: int, d_img: int, d_out: int, d_ws: int | None, stream: int
 
 def fht_plan_workspace_bytes_many(plan: int, n: int) -> int:
     return _lib.fht_plan_workspace_bytes_many(plan, n)
+
+
+def fht_forward_noalloc(plan: int, d_img: int, d_out: int, stream: int | None) -> None:
+    _check(_lib.fht_forward_noalloc(plan, d_img, d_out, stream), "fht_forward_noalloc")
 
 
 def fht_forward_many(plan: int, n: int, d_imgs: int, img_stride: int, d_outs: int,

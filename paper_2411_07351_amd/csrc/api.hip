@@ -27,6 +27,13 @@
 #include "kernels.hpp"
 #include "plan.hpp"
 
+// Workspace of fht_forward_noalloc, for callers that cannot allocate device
+// memory.  The runtime gives every device its own copy when it loads this
+// code object; it lives until the process ends.  Host code must not pass the
+// array's name to a kernel (on the host it only stands for the symbol): it
+// uses the device address hipGetSymbolAddress returns, kept per device.
+static __device__ __align__(256) unsigned char scratch[FHT_NOALLOC_WS_BYTES];
+
 namespace {
 
 using fht::Combo;
@@ -549,6 +556,15 @@ struct fht_plan_s {
         return FHT_OK;
     }
 
+    // Device tables already uploaded to device d, or null (never uploads).
+    const DevTables *find_tables(int d)
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (const DevTables &t : dev)
+            if (t.device == d) return &t;
+        return nullptr;
+    }
+
     const fht::AxisPlan &ax(int v) const { return view[v]->plan; }
 
     // The adjoint's host tables (caller holds mu).
@@ -786,6 +802,27 @@ bool injected_failure(fht_status *st)
         }
     }
     return false;
+}
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_at[kMaxScratchDevices];  // device d's copy of `scratch`, once looked up
+
+// Address of device d's scratch (d current), looked up on the first call on
+// that device.  Allocates nothing.
+fht_status scratch_on(int d, void **out)
+{
+    if (d < 0 || d >= kMaxScratchDevices) return FHT_ENODEV;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_at[d]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_status(e);
+        if (!p) return FHT_EHIP;
+        g_scratch_at[d] = p;
+    }
+    *out = g_scratch_at[d];
+    return FHT_OK;
 }
 
 // Host half of batch creation: the batch's launches and table blob.  The
@@ -1186,6 +1223,26 @@ fht_status fht_forward(fht_plan plan, const void *d_img, void *d_out, void *d_ws
     if (st == FHT_OK && injected_failure(&st)) return st;
     for (size_t l = 0; st == FHT_OK && l < plan->launches.size(); ++l)
         st = forward_one(plan, t, l, d_img, d_out, d_ws, stream);
+    return st;
+}
+
+fht_status fht_forward_noalloc(fht_plan plan, const void *d_img, void *d_out, void *stream)
+{
+    if (!plan || !d_img || !d_out) return FHT_EINVAL;
+    if (plan->ws_bytes > FHT_NOALLOC_WS_BYTES) return FHT_EINVAL;
+    int n = 0, d = -1;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0) return FHT_ENODEV;
+    const hipError_t e = hipGetDevice(&d);
+    if (e != hipSuccess) return hip_status(e);
+    const DevTables *t = plan->find_tables(d);
+    if (!t) return FHT_EINVAL;  // tables not on this device: fht_plan_upload allocates them
+    void *ws = nullptr;
+    fht_status st = FHT_OK;
+    if (plan->ws_bytes) st = scratch_on(d, &ws);
+    if (st == FHT_OK && injected_failure(&st)) return st;
+    // every workspace element is written before it is read: nothing to clear
+    for (size_t l = 0; st == FHT_OK && l < plan->launches.size(); ++l)
+        st = forward_one(plan, t, l, d_img, d_out, ws, stream);
     return st;
 }
 

@@ -202,3 +202,24 @@ def test_program_uploads_without_a_device():
         assert F.fht_plan_out_elems(h) == 2 * 2 * 64 * 80
     finally:
         F.fht_plan_destroy(h)
+
+
+def test_noalloc_entry_point_host_checks():
+    """fht_forward_noalloc: null pointers are rejected, the header's scratch
+    size is the binding's, and without a HIP device the call reports
+    FHT_ENODEV before anything is enqueued."""
+    with open(os.path.join(ROOT, "include", "fht.h")) as fh:
+        m = re.search(r"#define FHT_NOALLOC_WS_BYTES \(\(size_t\)(\d+) \* (\d+) \* (\d+)\)", fh.read())
+    assert m and int(m[1]) * int(m[2]) * int(m[3]) == F.NOALLOC_WS_BYTES
+    lib = ctypes.CDLL(F.LIB_PATH)
+    lib.fht_forward_noalloc.restype = ctypes.c_int32
+    lib.fht_forward_noalloc.argtypes = [ctypes.c_void_p] * 4
+    assert lib.fht_forward_noalloc(None, None, None, None) == -1
+    h = F.fht_plan_create(61, 47, F.FHT_U8, F.FHT_SPLIT_S, 15, None)
+    try:
+        assert lib.fht_forward_noalloc(h, None, None, None) == -1
+        import torch
+        if not torch.cuda.is_available():
+            assert F.STATUS[lib.fht_forward_noalloc(h, 16, 16, None)] == "FHT_ENODEV"
+    finally:
+        F.fht_plan_destroy(h)
