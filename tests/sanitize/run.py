@@ -43,7 +43,10 @@ def build(kind: str, out_dir: str) -> str:
     for name in SOURCES:
         obj = os.path.join(out_dir, name + ".o")
         if name.endswith(".hip"):
-            cmd = [HIPCC, "--offload-host-only", "--offload-arch=gfx950"] + common + \
+            # api.hip holds a device variable (the no-allocation scratch), so its
+            # device half is built too; the sanitizers apply to the host half only
+            only = [] if name == "api.hip" else ["--offload-host-only"]
+            cmd = [HIPCC] + only + ["--offload-arch=gfx950"] + common + \
                   _host_flags(kind) + ["-c", os.path.join(CSRC, name), "-o", obj]
         else:
             cmd = [CLANG] + common + _host_flags(kind) + ["-c", os.path.join(CSRC, name), "-o", obj]
