@@ -44,6 +44,8 @@ def _parse():
     ap.add_argument("--cols", type=int, default=1021)
     ap.add_argument("--split", default="S", choices=["S", "T"])
     ap.add_argument("--ragged", type=int, default=512, help="images in the ragged batch (0: skip)")
+    ap.add_argument("--tune", type=int, default=1,
+                    help="also run the ragged batch with autotuned per-size-class schedules")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU oracle sample budget (0 disables the cpu_baseline leg)")
     ap.add_argument("--diff-images", type=int, default=32,
@@ -338,6 +340,54 @@ def _differentiable(args, torch, F, WL):
                                     for v in (0, 1)) + 1}
 
 
+def _ragged_tuned(args, torch, F, shapes, rimgs, routs, rpx, stream):
+    """The ragged batch with a schedule per size class from the autotuner
+    (tuned here, outside the timed region, unless the cache already holds the
+    classes), replayed from a HIP graph like the default-schedule batch."""
+    import tempfile
+
+    from paper_2411_07351_amd import tuning as T
+    cache_dir = None
+    if "FHT_AUTOTUNE_CACHE" not in os.environ:
+        cache_dir = tempfile.mkdtemp(prefix="fht_tune_")
+        os.environ["FHT_AUTOTUNE_CACHE"] = os.path.join(cache_dir, "tune.json")
+    try:
+        scheds = T.autotune(rimgs, "S" if args.split == "S" else "T")
+        report = T.last_report
+        plans = T.plans_for(shapes, "u8", args.split, scheds)
+        batch = F.Batch(plans, rimgs, routs)
+        ws = batch.new_ws(rimgs[0].device)
+        graph = batch.capture(ws)
+        for _ in range(args.warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        a, b = _events(torch)
+        a.record(stream)
+        for _ in range(args.steps):
+            graph.replay()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / args.steps
+        changed = {}
+        for cls, sc in sorted(scheds.items()):
+            diff = {k: v for k, v in sc.items() if T.DEFAULT.get(k) != v}
+            if diff:
+                changed[cls] = diff
+        cls_rep = report["classes"].values()
+        return {"value": round(rpx / (ms * 1e-3) / 1e6, 1), "unit": "Mpixel/s",
+                "ms_per_step": round(ms, 3), "graph": True, "launches": batch.num_launches,
+                "classes": len(scheds),
+                "classes_tuned": sum(1 for r in cls_rep if r["source"] == "tuned"),
+                "tune_seconds": report["seconds"],
+                "class_ms_default_vs_tuned": [
+                    round(sum(r.get("default_ms") or 0 for r in cls_rep), 3),
+                    round(sum(r.get("ms") or 0 for r in cls_rep), 3)],
+                "schedules_changed": changed}
+    finally:
+        if cache_dir:
+            del os.environ["FHT_AUTOTUNE_CACHE"]
+
+
 def _events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
@@ -555,11 +605,15 @@ def main():
             "mpixels": round(rpx / 1e6, 2),
             "batched": {"value": round(rpx / (rbms * 1e-3) / 1e6, 1), "unit": "Mpixel/s",
                         "ms_per_step": round(rbms, 3), "graph": True,
-                        "launches": rb.num_launches},
+                        "launches": rb.num_launches, "schedule": "library default"},
             "plain": {"value": round(rpx / (rpms * 1e-3) / 1e6, 1), "unit": "Mpixel/s",
                       "ms_per_step": round(rpms, 3)},
         }
-        del rgraph, rb, rws, routs, rimgs
+        del rgraph, rb, rws, pws
+        if args.tune:
+            result["ragged"]["batched_tuned"] = _ragged_tuned(args, torch, F, shapes, rimgs,
+                                                              routs, rpx, stream)
+        del routs, rimgs
 
     if args.diff_images > 0:
         result["differentiable"] = _differentiable(args, torch, F, WL)

@@ -253,15 +253,16 @@ fht_status fht_forward_launch(fht_plan plan, int32_t launch, const void *d_img, 
 
 /*
  * Batched forward over n images of possibly different sizes (one plan each,
- * all of one dtype and split): one launch per fused pass for the whole batch
- * instead of per image.  fht_batch_create binds the device pointers and builds
+ * all of one dtype and split, with any schedules): one launch per fused pass
+ * and launch shape (element types, workgroup size, LDS size rounded up to
+ * 16 KiB) for the whole batch instead of per image.  fht_batch_create binds the device pointers and builds
  * the batch's device work list; fht_batch_run enqueues it (it may be captured
  * into a HIP graph).  d_ws must hold fht_batch_workspace_bytes bytes.
  *   plans  host array of n plans (each must outlive the batch)
  *   d_imgs host array of n device image pointers
  *   d_outs host array of n device output pointers (fht_plan_out_elems each)
- * Errors: FHT_EINVAL (also: plans with different workgroup sizes), FHT_EDTYPE
- * (dtypes or splits differ), FHT_ENOMEM, FHT_EHIP.
+ * Errors: FHT_EINVAL, FHT_EDTYPE (dtypes or splits differ), FHT_ENOMEM,
+ * FHT_EHIP.
  */
 fht_status fht_batch_create(fht_batch *out, const fht_plan *plans, int32_t n,
                             const void *const *d_imgs, void *const *d_outs);

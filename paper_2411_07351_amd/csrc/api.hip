@@ -831,15 +831,19 @@ fht_status scratch_on(int d, void **out)
 void batch_prepare(fht_batch_s *b, const fht_plan *plans, int32_t n, const void *const *d_imgs,
                    void *const *d_outs)
 {
-    // Batch launches keyed by (level, combination), in level order.
-    std::map<std::pair<int, int>, size_t> key;
+    // Batch launches keyed by (level, combination, threads, LDS bytes rounded
+    // up to 16 KiB), in level order: plans made with other schedules (the
+    // autotuner picks one per size class) get launches of their own shape, so
+    // that one plan's wide LDS use does not lower the occupancy of the others.
+    std::map<std::tuple<int, int, int, int>, size_t> key;
     size_t ws = 0;
     for (int i = 0; i < n; ++i) {
         const fht_plan p = plans[i];
         const size_t ws_base = ws;
         ws += align_up(p->ws_bytes, 256);
         for (const Launch &L : p->launches) {
-            const auto k = std::make_pair(L.level, static_cast<int>(L.combo));
+            const auto k = std::make_tuple(L.level, static_cast<int>(L.combo), L.threads,
+                                           static_cast<int>(align_up(L.lds_bytes, 16384)));
             auto found = key.find(k);
             if (found == key.end()) {
                 found = key.emplace(k, b->launches.size()).first;
@@ -917,10 +921,6 @@ fht_status batch_checks(const fht_plan *plans, int32_t n, const void *const *d_i
     for (int i = 1; i < n; ++i)
         if (plans[i]->dtype != plans[0]->dtype || plans[i]->split != plans[0]->split)
             return FHT_EDTYPE;
-    for (int i = 1; i < n; ++i)
-        if (plans[i]->threads != plans[0]->threads ||
-            plans[i]->threads_first != plans[0]->threads_first)
-            return FHT_EINVAL;
     return FHT_OK;
 }
 

@@ -1,18 +1,34 @@
-"""Schedules and a small autotuner for batched transforms.
+"""Autotuner of the fused-pass schedule, one schedule per size class.
 
 A schedule (``fht_schedule`` in ``include/fht.h``) only changes how the
-transform is tiled into fused passes, never its result.  The autotuner times
-candidate schedules on a given batch (device events on the working stream),
-keeps the fastest, and caches the choice in a JSON file keyed by GPU
-architecture, dtype, split rule and the batch's size classes, so that later
-batches of the same kind reuse it.  The cache is safe to delete.
+transform is tiled into fused passes, never its result.  Images are grouped
+into size classes, ``(ceil log2 rows, ceil log2 cols)``: the heights of the
+two order trees (proof of Theorem 1), which fix how many levels the passes
+have to cover, and so where the passes can be cut.  For every class present
+in a batch the tuner runs a coordinate descent over the knobs that change the
+pass structure or the tiles:
+
+* ``first_levels``: levels of the first pass (where it cuts the tree);
+* ``max_levels``: levels per later pass (how many passes, and where they cut);
+* ``s_tile_first``, ``s_tile``: position windows of the first and later passes;
+* ``t_tile``: slope rows per later work item;
+* ``threads``, ``threads_first``: workgroup sizes.
+
+Each candidate is timed on that class's images of the batch, run as a batch
+of their own (device events on the working stream, best of three groups).
+The winner is cached in a JSON file keyed by GPU architecture, dtype, split
+rule and class, so a later batch reuses it for every image of the class,
+whatever else the batch holds.  ``plans_for`` builds a batch's plans with
+the cached schedule of each image's class (the library default for classes
+never tuned).  The cache is safe to delete.
 """
 from __future__ import annotations
 
 import json
 import math
 import os
-from collections import Counter
+import time
+from collections import defaultdict
 from typing import Sequence
 
 from . import _binding as B
@@ -20,19 +36,19 @@ from . import _binding as B
 DEFAULT = dict(s_tile=192, s_tile_first=128, first_levels=5, max_levels=3, t_tile=16,
                threads=512, threads_first=512, lds_budget=65536)
 
-# A modest candidate set around the default: fused depth of the first pass,
-# window targets, slope tile and workgroup size of the later passes.
-CANDIDATES = [
-    DEFAULT,
-    dict(DEFAULT, t_tile=8, threads=256),
-    dict(DEFAULT, s_tile=128, threads=256),
-    dict(DEFAULT, s_tile=256, lds_budget=131072),
-    dict(DEFAULT, s_tile_first=192),
-    dict(DEFAULT, first_levels=4, s_tile_first=192),
-    dict(DEFAULT, threads_first=256),
-    dict(DEFAULT, max_levels=4),
-    dict(DEFAULT, max_levels=2),
-]
+# Knobs in the order the descent visits them, with the values it tries.
+KNOBS = (
+    ("first_levels", (4, 5, 6)),
+    ("max_levels", (2, 3, 4, 5)),
+    ("s_tile_first", (64, 128, 192)),
+    ("s_tile", (128, 192, 256)),
+    ("t_tile", (8, 16, 32)),
+    ("threads", (256, 512)),
+    ("threads_first", (256, 512)),
+)
+
+# Report of the last autotune() call (per class: source, schedule, timings).
+last_report: dict = {}
 
 
 def cache_path() -> str:
@@ -41,16 +57,29 @@ def cache_path() -> str:
 
 
 def size_class(rows: int, cols: int) -> str:
-    return f"{math.ceil(math.log2(max(rows, 2)))}x{math.ceil(math.log2(max(cols, 2)))}"
+    """Heights of the two order trees: ceil(log2 rows) x ceil(log2 cols)."""
+    def h(n):
+        return max(0, math.ceil(math.log2(n))) if n > 1 else 0
+    return f"{h(rows)}x{h(cols)}"
 
 
-def workload_key(shapes: Sequence[tuple], dtype: str, split: str) -> str:
+def _arch() -> str:
     import torch
-    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] \
-        if torch.cuda.is_available() else "cpu"
-    hist = Counter(size_class(r, c) for r, c in shapes)
-    classes = ",".join(f"{k}:{hist[k]}" for k in sorted(hist))
-    return f"{arch}|{dtype}|{split}|{classes}"
+    if not torch.cuda.is_available():
+        return "cpu"
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def class_key(cls: str, dtype: str, split: str, arch: str | None = None) -> str:
+    return f"{arch or _arch()}|{dtype}|{split}|{cls}"
+
+
+def _dtype_name(img) -> str:
+    return {1: "u8", 4: "f32", 8: "f64"}[img.element_size()]
+
+
+def _split_name(split) -> str:
+    return "S" if split in ("S", 0, B.FHT_SPLIT_S) else "T"
 
 
 def _load_cache() -> dict:
@@ -61,24 +90,27 @@ def _load_cache() -> dict:
         return {}
 
 
-def lookup(shapes, dtype="u8", split="S") -> dict | None:
-    entry = _load_cache().get(workload_key(shapes, dtype, split))
-    return dict(entry["schedule"]) if entry else None
-
-
-def _store(key: str, schedule: dict, timings: list) -> None:
+def _store(entries: dict) -> None:
     cache = _load_cache()
-    cache[key] = {"schedule": schedule, "timings_ms": timings}
+    cache.update(entries)
     path = cache_path()
-    os.makedirs(os.path.dirname(path), exist_ok=True)
-    tmp = path + ".tmp"
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = f"{path}.{os.getpid()}.tmp"
     with open(tmp, "w") as fh:
         json.dump(cache, fh, indent=1, sort_keys=True)
     os.replace(tmp, path)
 
 
-def time_batch(imgs, schedule: dict, split="S", reps: int = 3, warmup: int = 1) -> float:
-    """Milliseconds of one batched transform of `imgs` under `schedule`."""
+def lookup(rows: int, cols: int, dtype="u8", split="S") -> dict | None:
+    """The cached schedule of this shape's class, or None."""
+    entry = _load_cache().get(class_key(size_class(rows, cols), dtype, _split_name(split)))
+    return dict(entry["schedule"]) if entry else None
+
+
+def time_batch(imgs, schedule: dict, split="S", reps: int = 3, groups: int = 3,
+               warmup: int = 1) -> float:
+    """Milliseconds of one batched transform of `imgs` under `schedule`
+    (best of `groups` groups of `reps` runs)."""
     import torch
     plans, outs, cache = [], [], {}
     for img in imgs:
@@ -92,35 +124,96 @@ def time_batch(imgs, schedule: dict, split="S", reps: int = 3, warmup: int = 1) 
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         batch.run(ws)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        batch.run(ws)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / reps
-
-
-def autotune(imgs, split="S", candidates=None, reps: int = 3, use_cache: bool = True) -> dict:
-    """Fastest schedule for this batch (cached by workload kind)."""
-    shapes = [tuple(i.shape) for i in imgs]
-    dtype = {1: "u8", 4: "f32", 8: "f64"}[imgs[0].element_size()]
-    key = workload_key(shapes, dtype, split)
-    if use_cache:
-        hit = lookup(shapes, dtype, split)
-        if hit is not None:
-            return hit
-    timings = []
-    best, best_ms = None, float("inf")
-    for cand in candidates or CANDIDATES:
-        try:
-            ms = time_batch(imgs, cand, split, reps=reps)
-        except B.FhtError:
-            continue
-        timings.append({"schedule": cand, "ms": round(ms, 4)})
-        if ms < best_ms:
-            best, best_ms = dict(cand), ms
-    if best is None:
-        raise RuntimeError("no candidate schedule could be planned")
-    _store(key, best, timings)
+    best = float("inf")
+    for _ in range(groups):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            batch.run(ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / reps)
     return best
+
+
+def tune_class(imgs, split="S", knobs=KNOBS, reps: int = 3, start: dict | None = None):
+    """Coordinate descent over `knobs` for one class's images: returns the
+    best schedule and every (schedule, ms) tried."""
+    best = dict(start or DEFAULT)
+    tried = {}
+
+    def measure(sched):
+        key = json.dumps(sched, sort_keys=True)
+        if key not in tried:
+            try:
+                tried[key] = (dict(sched), time_batch(imgs, sched, split, reps=reps))
+            except (B.FhtError, ValueError):
+                tried[key] = (dict(sched), float("inf"))  # no plan fits: skipped
+        return tried[key][1]
+
+    best_ms = measure(best)
+    for name, values in knobs:
+        for v in values:
+            if v == best.get(name):
+                continue
+            cand = dict(best, **{name: v})
+            ms = measure(cand)
+            if ms < best_ms:
+                best, best_ms = cand, ms
+    timings = [{"schedule": s, "ms": round(ms, 4)} for s, ms in tried.values()
+               if ms != float("inf")]
+    return best, best_ms, timings
+
+
+def autotune(imgs, split="S", knobs=KNOBS, reps: int = 3, use_cache: bool = True,
+             max_images_per_class: int = 16) -> dict:
+    """Schedule per size class for the images of this batch, tuned for every
+    class not yet in the cache.  Returns {class: schedule}; ``last_report``
+    tells which classes were tuned and which came from the cache."""
+    global last_report
+    split = _split_name(split)
+    dtype = _dtype_name(imgs[0])
+    if any(_dtype_name(i) != dtype for i in imgs):
+        raise ValueError("one dtype per batch")
+    arch = _arch()
+    by_class = defaultdict(list)
+    for img in imgs:
+        by_class[size_class(img.shape[0], img.shape[1])].append(img)
+    cache = _load_cache() if use_cache else {}
+    out, report, new = {}, {}, {}
+    t0 = time.perf_counter()
+    for cls in sorted(by_class):
+        key = class_key(cls, dtype, split, arch)
+        if key in cache:
+            out[cls] = dict(cache[key]["schedule"])
+            report[cls] = {"source": "cache", "schedule": out[cls]}
+            continue
+        sub = by_class[cls][:max_images_per_class]
+        best, best_ms, timings = tune_class(sub, split, knobs, reps)
+        default_ms = next((t["ms"] for t in timings if t["schedule"] == DEFAULT), None)
+        out[cls] = best
+        new[key] = {"schedule": best, "timings_ms": timings, "images": len(sub)}
+        report[cls] = {"source": "tuned", "schedule": best, "ms": round(best_ms, 4),
+                       "default_ms": default_ms, "candidates": len(timings), "images": len(sub)}
+    if new:
+        _store(new)
+    last_report = {"classes": report, "seconds": round(time.perf_counter() - t0, 2)}
+    return out
+
+
+def plans_for(shapes: Sequence[tuple], dtype, split="S", schedules: dict | None = None):
+    """One plan per shape (shared between equal shapes), each with its size
+    class's schedule from `schedules` (as autotune returns) or the cache, the
+    library default otherwise."""
+    split_n = _split_name(split)
+    dname = {B.FHT_U8: "u8", B.FHT_F32: "f32", B.FHT_F64: "f64"}[B._dtype_code(dtype)]
+    plans, made = [], {}
+    for r, c in shapes:
+        if (r, c) not in made:
+            cls = size_class(r, c)
+            sched = (schedules or {}).get(cls)
+            if sched is None:
+                sched = lookup(r, c, dname, split_n)
+            made[(r, c)] = B.Plan(r, c, dtype, split_n, schedule=sched)
+        plans.append(made[(r, c)])
+    return plans
