@@ -109,7 +109,10 @@ fht_status fht_plan_create(fht_plan *out, int32_t rows, int32_t cols, int32_t dt
                            int32_t split, uint32_t quadrant_mask, const fht_schedule *sched);
 
 /* Frees host and device tables of a plan; NULL is ignored.  The caller
- * must make sure no enqueued work still uses the plan. */
+ * must make sure no enqueued work still uses the plan.  Device memory (of
+ * plans, and of lane-view programs the process-wide program cache drops) is
+ * released in groups of at least 64 MiB, because each release waits for the
+ * device: destroying a plan does not stall the streams. */
 void fht_plan_destroy(fht_plan plan);
 
 /* Elements of the output buffer: sum over selected q of W_q * H_q. */
@@ -253,9 +256,8 @@ fht_status fht_forward_launch(fht_plan plan, int32_t launch, const void *d_img, 
 
 /*
  * Batched forward over n images of possibly different sizes (one plan each,
- * all of one dtype and split, with any schedules): one launch per fused pass
- * and launch shape (element types, workgroup size, LDS size rounded up to
- * 16 KiB) for the whole batch instead of per image.  fht_batch_create binds the device pointers and builds
+ * all of one dtype and split, with any schedules): one launch per fused pass,
+ * element types and workgroup size for the whole batch instead of per image.  fht_batch_create binds the device pointers and builds
  * the batch's device work list; fht_batch_run enqueues it (it may be captured
  * into a HIP graph).  d_ws must hold fht_batch_workspace_bytes bytes.
  *   plans  host array of n plans (each must outlive the batch)
@@ -320,7 +322,8 @@ fht_status fht_batch_copy_images(fht_batch batch, const void *const *srcs, void 
  * -1 for V-/H-), it computes
  *   gimg = sum_q view_q^T ( g_q[x][y] = sum_t gout_q[t][(y - sigma_q pat_t(x)) mod H] )
  * by running the merges of Alg. 1 backwards, up to three tree levels per
- * gather launch.
+ * gather launch; the last gather of every quadrant runs in one final launch
+ * that also sums the quadrants into d_gimg.
  *   d_gout device, fht_plan_out_elems elements in fht_forward's output layout
  *   d_gimg device, rows x cols, overwritten
  *   d_ws   device, fht_plan_adjoint_workspace_bytes bytes (NULL when 0)

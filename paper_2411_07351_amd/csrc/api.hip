@@ -133,16 +133,51 @@ std::string kernel_name(Combo c, int threads, bool table)
            (pair ? "true" : "false") + ">";
 }
 
-// Device memory freed (on its own device) with the last view using it.
-std::shared_ptr<void> device_block(void *p, int device)
+// Program memory of lane views that left the plan cache.  hipFree waits for
+// the whole device, so blocks are not freed one by one as views leave the
+// cache (a burst of fresh plans in a full cache would stall every stream once
+// per eviction); they are collected and freed together once they pass
+// kRetireBytes.
+constexpr size_t kRetireBytes = size_t(64) << 20;
+
+struct Retired {
+    std::mutex mu;
+    std::vector<std::pair<int, void *>> blocks;  // (device, pointer)
+    size_t bytes = 0;
+};
+
+Retired &retired()
 {
-    return std::shared_ptr<void>(p, [device](void *q) {
-        int cur = 0;
-        const bool have = hipGetDevice(&cur) == hipSuccess;
-        (void)hipSetDevice(device);
-        (void)hipFree(q);
-        if (have) (void)hipSetDevice(cur);
-    });
+    static Retired *r = new Retired;  // never destroyed (see axis_cache)
+    return *r;
+}
+
+void retire(int device, void *p, size_t bytes)
+{
+    std::vector<std::pair<int, void *>> now;
+    {
+        Retired &r = retired();
+        std::lock_guard<std::mutex> lk(r.mu);
+        r.blocks.emplace_back(device, p);
+        r.bytes += bytes;
+        if (r.bytes < kRetireBytes) return;
+        now.swap(r.blocks);
+        r.bytes = 0;
+    }
+    int cur = 0;
+    const bool have = hipGetDevice(&cur) == hipSuccess;
+    for (const auto &b : now) {
+        (void)hipSetDevice(b.first);
+        (void)hipFree(b.second);
+    }
+    if (have) (void)hipSetDevice(cur);
+}
+
+// Device memory of `bytes` bytes, retired (on its own device) with the last
+// view using it.
+std::shared_ptr<void> device_block(void *p, int device, size_t bytes)
+{
+    return std::shared_ptr<void>(p, [device, bytes](void *q) { retire(device, q, bytes); });
 }
 
 // Batched program copies on one device: a non-blocking stream and two pinned
@@ -340,7 +375,7 @@ struct ViewProgs {
             if (o) (void)hipFree(o);
             return hip_status(e);
         }
-        *out = adopt(d, o, n_ops, device_block(o, d));
+        *out = adopt(d, o, n_ops, device_block(o, d, img.v.size() * sizeof(int32_t)));
         return FHT_OK;
     }
 
@@ -369,15 +404,19 @@ struct DevTables {
     bool adj_up = false;                         // adjoint tables uploaded (first adjoint call)
     int32_t *adj_offs[2] = {nullptr, nullptr};   // fused adjoint passes per lane view
     int32_t *adj_terms[2] = {nullptr, nullptr};
+    size_t bytes = 0;                            // device bytes of the tables above
 };
 
+// Retires a plan's device tables (see retire: a plan destroyed while other
+// work runs does not wait for the device).
 void free_tables(DevTables &t)
 {
+    const size_t share = t.bytes / 5 + 1;  // the retire threshold only needs a rough size
     for (int32_t *p : t.adj_offs)
-        if (p) (void)hipFree(p);
+        if (p) retire(t.device, p, share);
     for (int32_t *p : t.adj_terms)
-        if (p) (void)hipFree(p);
-    if (t.items_blob) (void)hipFree(t.items_blob);
+        if (p) retire(t.device, p, share);
+    if (t.items_blob) retire(t.device, t.items_blob, share);
     t = DevTables{};
 }
 
@@ -442,6 +481,8 @@ std::shared_ptr<ViewProgs> plan_view(int W, int H, int split, const fht::ElemRul
         auto made = std::make_shared<ViewProgs>();
         std::string err;
         if (!fht::plan_axis(W, Hk, split, rule, sc, &made->plan, &err)) return nullptr;
+        // views pushed out of the cache are destroyed after the lock is released
+        std::vector<std::shared_ptr<ViewProgs>> dropped;
         std::lock_guard<std::mutex> lk(c.mu);
         auto it = c.index.find(key);
         if (it != c.index.end()) {
@@ -454,6 +495,7 @@ std::shared_ptr<ViewProgs> plan_view(int W, int H, int split, const fht::ElemRul
             while (c.bytes > c.capacity && c.lru.size() > 1) {
                 c.bytes -= table_bytes(c.lru.back().second->plan);
                 c.index.erase(c.lru.back().first);
+                dropped.push_back(std::move(c.lru.back().second));
                 c.lru.pop_back();
             }
         }
@@ -544,6 +586,7 @@ struct fht_plan_s {
                 all.insert(all.end(), L.items.begin(), L.items.end());
             }
             e = upload(all, &t.items_blob);
+            t.bytes += all.size() * sizeof(int32_t);
             for (size_t l = 0; l < launches.size(); ++l)
                 t.items.push_back(t.items_blob ? t.items_blob + at[l] : nullptr);
         }
@@ -608,6 +651,7 @@ struct fht_plan_s {
             }
             e = upload(offs, &dt.adj_offs[v]);
             if (e == hipSuccess) e = upload(terms, &dt.adj_terms[v]);
+            dt.bytes += (offs.size() + terms.size()) * sizeof(int32_t);
         }
         if (e != hipSuccess) {
             for (int v = 0; v < 2; ++v) {
@@ -831,19 +875,18 @@ fht_status scratch_on(int d, void **out)
 void batch_prepare(fht_batch_s *b, const fht_plan *plans, int32_t n, const void *const *d_imgs,
                    void *const *d_outs)
 {
-    // Batch launches keyed by (level, combination, threads, LDS bytes rounded
-    // up to 16 KiB), in level order: plans made with other schedules (the
-    // autotuner picks one per size class) get launches of their own shape, so
-    // that one plan's wide LDS use does not lower the occupancy of the others.
-    std::map<std::tuple<int, int, int, int>, size_t> key;
+    // Batch launches keyed by (level, combination, workgroup size), in level
+    // order: plans made with other workgroup sizes (the autotuner picks a
+    // schedule per size class) get launches of their own.  A launch takes the
+    // largest LDS size of its items.
+    std::map<std::tuple<int, int, int>, size_t> key;
     size_t ws = 0;
     for (int i = 0; i < n; ++i) {
         const fht_plan p = plans[i];
         const size_t ws_base = ws;
         ws += align_up(p->ws_bytes, 256);
         for (const Launch &L : p->launches) {
-            const auto k = std::make_tuple(L.level, static_cast<int>(L.combo), L.threads,
-                                           static_cast<int>(align_up(L.lds_bytes, 16384)));
+            const auto k = std::make_tuple(L.level, static_cast<int>(L.combo), L.threads);
             auto found = key.find(k);
             if (found == key.end()) {
                 found = key.emplace(k, b->launches.size()).first;
@@ -1195,7 +1238,7 @@ fht_status fht_plan_upload_programs_many(const fht_plan *plans, int32_t n)
         void *block = nullptr;
         e = hipMalloc(&block, total);
         if (e != hipSuccess) return hip_status(e);
-        const std::shared_ptr<void> mem = device_block(block, d);
+        const std::shared_ptr<void> mem = device_block(block, d, total);
         {
             CopyLane &L = copy_lane(d);
             std::lock_guard<std::mutex> lk(L.mu);
@@ -1504,21 +1547,23 @@ fht_status fht_adjoint_many(fht_plan plan, int32_t n, const void *d_gouts, int64
     hipStream_t hs = static_cast<hipStream_t>(stream);
     char *ws = static_cast<char *>(d_ws);
     const char *gout = static_cast<const char *>(d_gouts);
+    // Every quadrant's passes but its last run as gather launches; the last
+    // ones run in the final launch, which also sums into the image gradient.
     int max_passes = 0;
     for (int q = 0; q < 4; ++q)
         if (plan->qmask & (1u << q))
             max_passes = std::max(max_passes, plan->adj_npass[q >> 1]);
-    for (int k = 0; k < max_passes; ++k) {
+    for (int k = 0; k + 1 < max_passes; ++k) {
         fht::AdjArgs a;
         std::memset(&a, 0, sizeof(a));
         a.src_stride = k == 0 ? gout_stride : ws_stride;
         a.dst_stride = ws_stride;
-        int nj = 0, max_w = 0;
+        int nj = 0, max_w = 0, max_h = 0;
         for (int q = 0; q < 4; ++q) {
             if (!(plan->qmask & (1u << q))) continue;
             const int v = q >> 1;
             const fht::AdjointAxis &ax = plan->adj[v];
-            if (plan->adj_npass[v] <= k) continue;
+            if (plan->adj_npass[v] <= k + 1) continue;
             fht::AdjJob &j = a.job[nj++];
             j.src = k == 0 ? static_cast<const void *>(gout + plan->out_off[q] * eb)
                            : static_cast<const void *>(ws + plan->adj_ws_off[q][(k - 1) & 1]);
@@ -1529,11 +1574,12 @@ fht_status fht_adjoint_many(fht_plan plan, int32_t n, const void *d_gouts, int64
             j.H = (q >> 1) ? plan->R : plan->C;
             j.mirror_in = (k == 0 && (q & 1)) ? 1 : 0;
             max_w = std::max(max_w, ax.W);
+            max_h = std::max(max_h, j.H);
         }
-        const hipError_t e = fht::launch_adjoint_step(real, a, nj, max_w, hs, n);
+        const hipError_t e = fht::launch_adjoint_step(real, a, nj, max_w, hs, n, max_h);
         if (e != hipSuccess) return hip_status(e);
     }
-    fht::CombineArgs c;
+    fht::FinalArgs c;
     std::memset(&c, 0, sizeof(c));
     c.R = plan->R;
     c.C = plan->C;
@@ -1541,14 +1587,26 @@ fht_status fht_adjoint_many(fht_plan plan, int32_t n, const void *d_gouts, int64
     c.dst_stride = gimg_stride;
     for (int q = 0; q < 4; ++q) {
         if (!(plan->qmask & (1u << q))) continue;
-        const int L = plan->adj_npass[q >> 1];
-        // after the steps a negative-slope quadrant is in the mirrored frame
-        c.src[q] = L > 0 ? static_cast<const void *>(ws + plan->adj_ws_off[q][(L - 1) & 1])
-                         : static_cast<const void *>(gout + plan->out_off[q] * eb);
-        c.src_stride[q] = L > 0 ? ws_stride : gout_stride;
-        c.mirror[q] = (L > 0 && (q & 1)) ? 1 : 0;
+        const int v = q >> 1;
+        const int L = plan->adj_npass[v];
+        fht::FinalJob &f = c.q[q];
+        if (L == 0) {  // no tree levels: the lane gradient is the output gradient
+            f.src = gout + plan->out_off[q] * eb;
+            f.src_stride = gout_stride;
+            continue;
+        }
+        // pass L - 1 reads the output gradient (L = 1, at mirrored positions
+        // for negative slopes) or the rows pass L - 2 wrote
+        f.src = L == 1 ? static_cast<const void *>(gout + plan->out_off[q] * eb)
+                       : static_cast<const void *>(ws + plan->adj_ws_off[q][(L - 2) & 1]);
+        f.src_stride = L == 1 ? gout_stride : ws_stride;
+        f.offs = t->adj_offs[v] + plan->adjp_offs[v][L - 1];
+        f.terms = reinterpret_cast<const int2 *>(t->adj_terms[v]) + plan->adjp_terms[v][L - 1];
+        f.in_mirror = (L == 1 && (q & 1)) ? 1 : 0;
+        // after its passes a negative-slope quadrant is in the mirrored frame
+        f.out_mirror = (q & 1) ? 1 : 0;
     }
-    return hip_status(fht::launch_adjoint_combine(real, c, hs, n));
+    return hip_status(fht::launch_adjoint_final(real, c, hs, n));
 }
 
 fht_status fht_adjoint(fht_plan plan, const void *d_gout, void *d_gimg, void *d_ws, void *stream)

@@ -94,17 +94,23 @@ struct AdjArgs {
     int64_t src_stride, dst_stride;
 };
 
-// Sum of the quadrants' lane gradients into the image gradient (R x C):
-// quadrants 0/1 have lanes = rows, 2/3 lanes = columns; `mirror` reads the
-// positions at (H - y) mod H.
-struct CombineArgs {
-    const void *src[kInlineJobs];  // null: quadrant absent
-    int32_t mirror[kInlineJobs];
+// The last gather pass of every quadrant fused with the sum into the image
+// gradient (R x C): one job per quadrant.
+struct FinalJob {
+    const void *src;        // rows the quadrant's last pass reads; null: quadrant absent
+    const int32_t *offs;    // W + 1 term offsets of that pass; null: no tree levels (W = 1),
+                            // the lane gradient is src itself
+    const int2 *terms;      // {source row, shift mod H}
+    int64_t src_stride;     // bytes between images of a same-shape batch
+    int32_t in_mirror;      // src is read at mirrored positions (the last pass is the first)
+    int32_t out_mirror;     // the quadrant's lane gradient is in the mirrored frame
+};
+
+struct FinalArgs {
+    FinalJob q[kInlineJobs];  // quadrants 0..3 (lanes = rows for 0/1, columns for 2/3)
     int32_t R, C;
     void *dst;
-    // same-shape image batches (grid.z = image): bytes between images of each
-    // source and of the destination
-    int64_t src_stride[kInlineJobs], dst_stride;
+    int64_t dst_stride;
 };
 
 enum class Real { F32, F64 };
@@ -134,9 +140,11 @@ enum class PeakElem { I32, F32, F64 };
 
 hipError_t launch_peaks(PeakElem elem, const PeakArgs &args, size_t max_elems, hipStream_t stream);
 
+// max_h: the largest H of the jobs (rows of up to 512 positions go in one
+// round of loads).
 hipError_t launch_adjoint_step(Real real, const AdjArgs &args, int n_jobs, int max_w,
-                               hipStream_t stream, int n_images = 1);
-hipError_t launch_adjoint_combine(Real real, const CombineArgs &args, hipStream_t stream,
-                                  int n_images = 1);
+                               hipStream_t stream, int n_images = 1, int max_h = 0);
+hipError_t launch_adjoint_final(Real real, const FinalArgs &args, hipStream_t stream,
+                                int n_images = 1);
 
 }  // namespace fht

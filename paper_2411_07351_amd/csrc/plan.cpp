@@ -465,8 +465,18 @@ bool plan_axis(int W, int H, int split, const ElemRule &rule, const Schedule &sc
     out->passes.clear();
     int lin = 0;
     do {
-        const int maxlv = (lin == 0) ? std::min(sched.first_levels, kMaxFirstLevels)
-                                     : std::min(sched.max_levels, kMaxSteps);
+        int maxlv = (lin == 0) ? std::min(sched.first_levels, kMaxFirstLevels)
+                               : std::min(sched.max_levels, kMaxSteps);
+        // A later pass takes one more level than the schedule asks for
+        // wherever that saves a whole pass (an HBM round trip of every row):
+        // when the remaining levels r need fewer passes of m + 1 levels than
+        // of m (r = 4: 3 + 1 becomes 4; r = 7: 3 + 3 + 1 becomes 4 + 3).  The
+        // pass still takes fewer levels if the LDS budget requires it.
+        if (lin > 0) {
+            const int r = L - lin;
+            if (maxlv + 1 <= kMaxSteps && (r + maxlv - 1) / maxlv > (r + maxlv) / (maxlv + 1))
+                ++maxlv;
+        }
         const int target = (lin == 0) ? sched.s_tile_first : sched.s_tile;
         bool found = false;
         Pass best;

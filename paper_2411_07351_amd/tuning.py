@@ -16,9 +16,13 @@ pass structure or the tiles:
 
 Each candidate is timed on that class's images of the batch, run as a batch
 of their own (device events on the working stream, best of three groups).
-The winner is cached in a JSON file keyed by GPU architecture, dtype, split
-rule and class, so a later batch reuses it for every image of the class,
-whatever else the batch holds.  ``plans_for`` builds a batch's plans with
+A class's winner then has to pay off in the whole batch, where the classes
+share launches: starting from the library default for every class, the
+classes are visited largest first, and a class keeps its winner only if the
+whole batch gets faster with it (other workgroup sizes, for instance, add
+launches of their own).  The result is cached in a JSON file keyed by GPU
+architecture, dtype, split rule and class, so a later batch reuses it for
+every image of the class.  ``plans_for`` builds a batch's plans with
 the cached schedule of each image's class (the library default for classes
 never tuned).  The cache is safe to delete.
 """
@@ -111,14 +115,20 @@ def time_batch(imgs, schedule: dict, split="S", reps: int = 3, groups: int = 3,
                warmup: int = 1) -> float:
     """Milliseconds of one batched transform of `imgs` under `schedule`
     (best of `groups` groups of `reps` runs)."""
-    import torch
-    plans, outs, cache = [], [], {}
+    plans, cache = [], {}
     for img in imgs:
         key = (tuple(img.shape), img.dtype)
         if key not in cache:
             cache[key] = B.Plan(img.shape[0], img.shape[1], img.dtype, split, schedule=schedule)
         plans.append(cache[key])
-        outs.append(cache[key].new_out(img.device))
+    return time_plans(imgs, plans, reps, groups, warmup)
+
+
+def time_plans(imgs, plans, reps: int = 3, groups: int = 3, warmup: int = 1, outs=None) -> float:
+    """Milliseconds of one batched transform of `imgs` with one plan each."""
+    import torch
+    if outs is None:
+        outs = [p.new_out(i.device) for p, i in zip(plans, imgs)]
     batch = B.Batch(plans, imgs, outs)
     ws = batch.new_ws(imgs[0].device)
     stream = torch.cuda.current_stream()
@@ -165,11 +175,50 @@ def tune_class(imgs, split="S", knobs=KNOBS, reps: int = 3, start: dict | None =
     return best, best_ms, timings
 
 
+def _in_batch(imgs, split, start: dict, proposals: dict, classes_of: list, reps: int):
+    """From the schedules `start` (one per class), keeps, largest class
+    first, each class's proposal that makes the whole batch faster (by more
+    than 0.3 %).  Returns the schedules and the batch milliseconds with
+    `start` and with the kept proposals."""
+    plan_cache = {}
+
+    def plans_with(scheds):
+        plans = []
+        for img, cls in zip(imgs, classes_of):
+            sc = scheds[cls]
+            key = (tuple(img.shape), json.dumps(sc, sort_keys=True))
+            if key not in plan_cache:
+                plan_cache[key] = B.Plan(img.shape[0], img.shape[1], img.dtype, split, schedule=sc)
+            plans.append(plan_cache[key])
+        return plans
+
+    cur = dict(start)
+    plans = plans_with(cur)
+    outs = [p.new_out(i.device) for p, i in zip(plans, imgs)]
+    base = default_ms = time_plans(imgs, plans, reps, outs=outs)
+    px = defaultdict(int)
+    for img, cls in zip(imgs, classes_of):
+        px[cls] += img.shape[0] * img.shape[1]
+    kept = []
+    for cls in sorted(proposals, key=lambda c: -px[c]):
+        if proposals[cls] == cur[cls]:
+            continue
+        trial = dict(cur)
+        trial[cls] = proposals[cls]
+        ms = time_plans(imgs, plans_with(trial), reps, outs=outs)
+        if ms < base * 0.997:
+            cur, base = trial, ms
+            kept.append(cls)
+    return cur, default_ms, base, kept
+
+
 def autotune(imgs, split="S", knobs=KNOBS, reps: int = 3, use_cache: bool = True,
-             max_images_per_class: int = 16) -> dict:
+             max_images_per_class: int = 16, in_batch: bool = True) -> dict:
     """Schedule per size class for the images of this batch, tuned for every
-    class not yet in the cache.  Returns {class: schedule}; ``last_report``
-    tells which classes were tuned and which came from the cache."""
+    class not yet in the cache (each class alone, then, with ``in_batch``,
+    kept only where it speeds up the whole batch).  Returns {class:
+    schedule}; ``last_report`` tells which classes were tuned and which came
+    from the cache."""
     global last_report
     split = _split_name(split)
     dtype = _dtype_name(imgs[0])
@@ -192,12 +241,29 @@ def autotune(imgs, split="S", knobs=KNOBS, reps: int = 3, use_cache: bool = True
         best, best_ms, timings = tune_class(sub, split, knobs, reps)
         default_ms = next((t["ms"] for t in timings if t["schedule"] == DEFAULT), None)
         out[cls] = best
-        new[key] = {"schedule": best, "timings_ms": timings, "images": len(sub)}
+        new[key] = {"schedule": best, "alone": best, "timings_ms": timings, "images": len(sub)}
         report[cls] = {"source": "tuned", "schedule": best, "ms": round(best_ms, 4),
                        "default_ms": default_ms, "candidates": len(timings), "images": len(sub)}
+    batch_rep = None
+    fresh = [c for c in report if report[c]["source"] == "tuned"]
+    if in_batch and fresh:
+        classes_of = [size_class(i.shape[0], i.shape[1]) for i in imgs]
+        start = {c: (dict(DEFAULT) if c in fresh else out[c]) for c in out}
+        _, d_ms, t_ms, kept = _in_batch(imgs, split, start, {c: out[c] for c in fresh},
+                                        classes_of, reps)
+        for c in fresh:
+            if c not in kept:
+                out[c] = dict(DEFAULT)
+            key = class_key(c, dtype, split, arch)
+            new[key]["schedule"] = out[c]
+            new[key]["kept_in_batch"] = c in kept
+            report[c]["schedule"] = out[c]
+            report[c]["kept_in_batch"] = c in kept
+        batch_rep = {"default_ms": round(d_ms, 4), "tuned_ms": round(t_ms, 4), "kept": kept}
     if new:
         _store(new)
-    last_report = {"classes": report, "seconds": round(time.perf_counter() - t0, 2)}
+    last_report = {"classes": report, "batch": batch_rep,
+                   "seconds": round(time.perf_counter() - t0, 2)}
     return out
 
 

@@ -1,7 +1,8 @@
 """Full-element parity for the widest lane views.
 
-Plans of 2049 lanes and more run four fused passes (4096 lanes) or five
-(sides above 4096, up to the 65536 that fht_plan_create accepts); every
+Plans of 2049 lanes and more run three fused passes (up to 8192 lanes: a
+later pass takes four tree levels where that saves a pass) or four (16384
+and 65536 lanes, up to the 65536 that fht_plan_create accepts); every
 output element is compared, not a sample: with classic Brady-Yong at
 4096 x 4096 (Sec. 3: both splits coincide with it at powers of two) and with
 the C oracle's direct sums elsewhere.  uint8 bit-exact (int32), float32
@@ -104,4 +105,7 @@ def test_sides_above_4096_every_output(kind, shape, split):
         ref, ab = native.hough4_f64(img.astype(np.float64), sp)
         for q in range(4):
             _close(got[q], ref[q], ab[q])
-    assert max(F.fht_plan_num_passes(plan.handle, v) for v in (0, 1)) >= 4
+    # 8191 lanes: 13 tree levels in 3 passes (5 + 4 + 4); 16384 and 65536
+    # lanes: 4 passes
+    assert max(F.fht_plan_num_passes(plan.handle, v) for v in (0, 1)) >= \
+        (4 if max(R, C) >= 16384 else 3)
