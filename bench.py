@@ -506,6 +506,10 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": round(traffic, 0) if traffic is not None else None,
+            "traffic_note": "FETCH_SIZE + WRITE_SIZE per launch (profiles/), scaled by a 1 GiB "
+                            "device copy; these count L2<->fabric requests, hits in the 256 MB "
+                            "memory-side cache included, and the plain path's working set (one "
+                            "image, its output, a reused workspace) fits that cache",
             "bytes_per_launch": dom_bytes,
             "avg_launch_us": round(launch_ms[dom] * 1e3, 2),
             "launch_avg_us": [round(m * 1e3, 2) for m in launch_ms],
