@@ -12,7 +12,9 @@
 // gather of every quadrant runs in one final launch that also adds the
 // quadrants' lane gradients into the image gradient, transposing the
 // column-lane quadrants through LDS, so the last lane gradients never go to
-// memory.  Memory-bound gathers: no MFMA.
+// memory; where that launch would have too few tiles to fill the chip (one
+// small image), the last gathers run as their own launch and a combine
+// launch adds the lane gradients.  Memory-bound gathers: no MFMA.
 #include "kernels.hpp"
 
 namespace fht {
@@ -214,6 +216,74 @@ __device__ __forceinline__ void view_gather_rows(const FinalJob &a, const FinalJ
     for (int r = 0; r < NR; ++r) out[r] = acc[r];
 }
 
+
+// grad[i][j] = sum over present quadrants of their lane gradient at (i, j):
+// q0/q1 read g[i][j'] (lanes are rows), q2/q3 read g[j][i'] (lanes are
+// columns), primes marking mirrored positions where asked.  A block covers a
+// 64 x 64 tile; column-lane quadrants are staged transposed in LDS.
+template <typename T>
+__global__ void __launch_bounds__(256) adj_combine_kernel(CombineArgs args)
+{
+    __shared__ T tile[kTile][kTile + 1];
+    constexpr int KR = kTile / 4;  // rows per thread
+    const int R = args.R, C = args.C;
+    const int i0 = blockIdx.y * kTile, j0 = blockIdx.x * kTile;
+    const int tj = threadIdx.x & 63, ti = threadIdx.x >> 6;  // 64 x 4 threads
+    const int64_t b = blockIdx.z;  // image of a same-shape batch
+    auto source = [&](int q) -> const T * {
+        return args.src[q] ? reinterpret_cast<const T *>(static_cast<const char *>(args.src[q]) +
+                                                         b * args.src_stride[q])
+                           : nullptr;
+    };
+    // Row-lane quadrants: every load of the thread is issued before the adds.
+    const T *g0 = source(0), *g1 = source(1);
+    const int j = j0 + tj;
+    T acc[KR];
+    {
+        const int jc = min(j, C - 1);
+        const int jj0 = (args.mirror[0] && jc != 0) ? C - jc : jc;
+        const int jj1 = (args.mirror[1] && jc != 0) ? C - jc : jc;
+        T v0[KR], v1[KR];
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+            const size_t row = static_cast<size_t>(min(i0 + ti + 4 * k, R - 1)) * C;
+            v0[k] = g0 ? g0[row + jj0] : T(0);
+            v1[k] = g1 ? g1[row + jj1] : T(0);
+        }
+#pragma unroll
+        for (int k = 0; k < KR; ++k) acc[k] = v0[k] + v1[k];
+    }
+    // Column-lane quadrants: both are staged, summed, as tile[a][c] =
+    // g[j0 + a][i'(i0 + c)] with threads along c, then read transposed.
+    const T *g2 = source(2), *g3 = source(3);
+    if (g2 || g3) {  // uniform across the block
+        const int c = threadIdx.x & 63;
+        const int i = min(i0 + c, R - 1);
+        const int ii2 = (args.mirror[2] && i != 0) ? R - i : i;
+        const int ii3 = (args.mirror[3] && i != 0) ? R - i : i;
+        T v2[KR], v3[KR];
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+            const size_t row = static_cast<size_t>(min(j0 + ti + 4 * k, C - 1)) * R;
+            v2[k] = g2 ? g2[row + ii2] : T(0);
+            v3[k] = g3 ? g3[row + ii3] : T(0);
+        }
+#pragma unroll
+        for (int k = 0; k < KR; ++k) tile[ti + 4 * k][c] = v2[k] + v3[k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KR; ++k) acc[k] += tile[tj][ti + 4 * k];
+    }
+    T *out = reinterpret_cast<T *>(static_cast<char *>(args.dst) + b * args.dst_stride);
+    if (j < C) {
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+            const int i = i0 + ti + 4 * k;
+            if (i < R) out[static_cast<size_t>(i) * C + j] = acc[k];
+        }
+    }
+}
+
 // grad[i][j] = sum over present quadrants of their lane gradient at (i, j),
 // each computed here by its last gather: q0/q1 at lane i, position j'
 // (lanes are rows), q2/q3 at lane j, position i' (lanes are columns), primes
@@ -298,6 +368,19 @@ hipError_t launch_adjoint_step(Real real, const AdjArgs &args, int n_jobs, int m
         if (wide) adj_step_kernel<float, 8><<<grid, block, 0, stream>>>(args);
         else adj_step_kernel<float, 4><<<grid, block, 0, stream>>>(args);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_combine(Real real, const CombineArgs &args, hipStream_t stream,
+                                  int n_images)
+{
+    if (n_images <= 0) return hipSuccess;
+    const dim3 grid((args.C + kTile - 1) / kTile, (args.R + kTile - 1) / kTile, n_images),
+        block(256);
+    if (real == Real::F64)
+        adj_combine_kernel<double><<<grid, block, 0, stream>>>(args);
+    else
+        adj_combine_kernel<float><<<grid, block, 0, stream>>>(args);
     return hipGetLastError();
 }
 

@@ -67,6 +67,9 @@ constexpr int kNarrowWidth = 257;
 
 // Tree levels per adjoint gather launch.
 constexpr int kAdjointFuse = 3;
+// The fused final adjoint launch needs at least this many 64 x 64 tiles (one
+// per compute unit); below, the last gathers and the combine run apart.
+constexpr int64_t kFinalMinTiles = 256;
 
 // Element types of pass p of an axis plan (see fht::Combo); `pair` selects
 // the quadrant-pair form.
@@ -1548,12 +1551,17 @@ fht_status fht_adjoint_many(fht_plan plan, int32_t n, const void *d_gouts, int64
     char *ws = static_cast<char *>(d_ws);
     const char *gout = static_cast<const char *>(d_gouts);
     // Every quadrant's passes but its last run as gather launches; the last
-    // ones run in the final launch, which also sums into the image gradient.
+    // ones run in the final launch, which also sums into the image gradient,
+    // when its 64 x 64 tiles give every compute unit one; otherwise the last
+    // gathers run as their own launch and a combine launch adds up.
     int max_passes = 0;
     for (int q = 0; q < 4; ++q)
         if (plan->qmask & (1u << q))
             max_passes = std::max(max_passes, plan->adj_npass[q >> 1]);
-    for (int k = 0; k + 1 < max_passes; ++k) {
+    const int64_t tiles = static_cast<int64_t>((plan->R + 63) / 64) * ((plan->C + 63) / 64) * n;
+    const bool fuse_last = tiles >= kFinalMinTiles;
+    const int gathers = fuse_last ? max_passes - 1 : max_passes;
+    for (int k = 0; k < gathers; ++k) {
         fht::AdjArgs a;
         std::memset(&a, 0, sizeof(a));
         a.src_stride = k == 0 ? gout_stride : ws_stride;
@@ -1563,7 +1571,7 @@ fht_status fht_adjoint_many(fht_plan plan, int32_t n, const void *d_gouts, int64
             if (!(plan->qmask & (1u << q))) continue;
             const int v = q >> 1;
             const fht::AdjointAxis &ax = plan->adj[v];
-            if (plan->adj_npass[v] <= k + 1) continue;
+            if (plan->adj_npass[v] <= (fuse_last ? k + 1 : k)) continue;
             fht::AdjJob &j = a.job[nj++];
             j.src = k == 0 ? static_cast<const void *>(gout + plan->out_off[q] * eb)
                            : static_cast<const void *>(ws + plan->adj_ws_off[q][(k - 1) & 1]);
@@ -1578,6 +1586,24 @@ fht_status fht_adjoint_many(fht_plan plan, int32_t n, const void *d_gouts, int64
         }
         const hipError_t e = fht::launch_adjoint_step(real, a, nj, max_w, hs, n, max_h);
         if (e != hipSuccess) return hip_status(e);
+    }
+    if (!fuse_last) {
+        fht::CombineArgs c;
+        std::memset(&c, 0, sizeof(c));
+        c.R = plan->R;
+        c.C = plan->C;
+        c.dst = d_gimgs;
+        c.dst_stride = gimg_stride;
+        for (int q = 0; q < 4; ++q) {
+            if (!(plan->qmask & (1u << q))) continue;
+            const int L = plan->adj_npass[q >> 1];
+            // after the steps a negative-slope quadrant is in the mirrored frame
+            c.src[q] = L > 0 ? static_cast<const void *>(ws + plan->adj_ws_off[q][(L - 1) & 1])
+                             : static_cast<const void *>(gout + plan->out_off[q] * eb);
+            c.src_stride[q] = L > 0 ? ws_stride : gout_stride;
+            c.mirror[q] = (L > 0 && (q & 1)) ? 1 : 0;
+        }
+        return hip_status(fht::launch_adjoint_combine(real, c, hs, n));
     }
     fht::FinalArgs c;
     std::memset(&c, 0, sizeof(c));

@@ -94,6 +94,19 @@ struct AdjArgs {
     int64_t src_stride, dst_stride;
 };
 
+// Sum of the quadrants' lane gradients into the image gradient (R x C):
+// quadrants 0/1 have lanes = rows, 2/3 lanes = columns; `mirror` reads the
+// positions at (H - y) mod H.
+struct CombineArgs {
+    const void *src[kInlineJobs];  // null: quadrant absent
+    int32_t mirror[kInlineJobs];
+    int32_t R, C;
+    void *dst;
+    // same-shape image batches (grid.z = image): bytes between images of each
+    // source and of the destination
+    int64_t src_stride[kInlineJobs], dst_stride;
+};
+
 // The last gather pass of every quadrant fused with the sum into the image
 // gradient (R x C): one job per quadrant.
 struct FinalJob {
@@ -146,5 +159,7 @@ hipError_t launch_adjoint_step(Real real, const AdjArgs &args, int n_jobs, int m
                                hipStream_t stream, int n_images = 1, int max_h = 0);
 hipError_t launch_adjoint_final(Real real, const FinalArgs &args, hipStream_t stream,
                                 int n_images = 1);
+hipError_t launch_adjoint_combine(Real real, const CombineArgs &args, hipStream_t stream,
+                                  int n_images = 1);
 
 }  // namespace fht
