@@ -138,7 +138,8 @@ int32_t fht_plan_num_launches(fht_plan plan);
 fht_status fht_plan_launch_info(fht_plan plan, int32_t launch, int32_t *level,
                                 int64_t *bytes_in, int64_t *bytes_out, int32_t *n_items);
 
-/* Additions of the plan's forward transform, summed over its quadrants:
+/* Inspection (tests and tools; not needed to run the transform).
+ * Additions of the plan's forward transform, summed over its quadrants:
  * *adds_tree is the count of Alg. 1 (every non-leaf node of width w of the
  * order tree adds w rows of H positions: Theorem 1's f(n) for n x n);
  * *adds_executed is what the fused kernels add, whole 64-position chunks of
@@ -331,14 +332,16 @@ fht_status fht_batch_copy_images(fht_batch batch, const void *const *srcs, void 
  * FHT_ENOMEM, FHT_EHIP.
  */
 size_t fht_plan_adjoint_workspace_bytes(fht_plan plan);
-/* Host view of the adjoint's gather steps of lane view v (0: lanes are rows,
+/* Inspection (tests and tools; not needed to run the transform).
+ * Host view of the adjoint's gather steps of lane view v (0: lanes are rows,
  * 1: columns), valid while the plan lives: *levels steps of *lanes tasks of 4
  * ints {p0, n, r0, right}; step k, row x:
  *   g_out[x][s] = sum_{j<n} g_in[p0 + j][(s - (right ? r0 + j : 0)) mod H].
  * Errors: FHT_EINVAL, FHT_EDTYPE (uint8 plan). */
 fht_status fht_plan_adjoint_tasks(fht_plan plan, int32_t v, const int32_t **tasks,
                                   int32_t *levels, int32_t *lanes);
-/* The gather launches fht_adjoint runs for lane view v: those steps composed
+/* Inspection (tests and tools; not needed to run the transform).
+ * The gather launches fht_adjoint runs for lane view v: those steps composed
  * a few levels at a time.  fht_plan_adjoint_num_passes returns their number
  * (-1 for a bad view or a uint8 plan); pass `pass` covers *levels steps:
  *   g_out[x][s] = sum_{i in [offs[x], offs[x+1])} g_in[terms[2i]][(s - terms[2i+1]) mod H]
@@ -383,8 +386,8 @@ fht_status fht_peaks(fht_plan plan, const void *d_out, int32_t k, int32_t radius
 
 /*
  * Fault injection for tests of error handling: the next `count` calls that
- * enqueue device work (fht_forward, fht_forward_many, fht_forward_launch,
- * fht_adjoint, fht_adjoint_many, fht_peaks,
+ * enqueue device work (fht_forward, fht_forward_noalloc, fht_forward_many,
+ * fht_forward_launch, fht_adjoint, fht_adjoint_many, fht_peaks,
  * fht_batch_upload, fht_batch_upload_staged, fht_batch_run, fht_batch_run_launch) return
  * `code` (an fht_status value) after checking their
  * arguments and before enqueuing anything.  count <= 0 or code == FHT_OK
@@ -393,6 +396,7 @@ fht_status fht_peaks(fht_plan plan, const void *d_out, int32_t k, int32_t radius
 void fht_debug_fail_next(int32_t code, int32_t count);
 
 /*
+ * Inspection (tests and tools; not needed to run the transform).
  * Host view of a plan's tables, for inspection and tests of the planner.
  * Quadrant view v = 0 (lanes are image rows) or 1 (lanes are image columns).
  * fht_plan_num_passes returns the number of fused passes of view v (or -1).

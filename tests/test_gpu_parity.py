@@ -25,11 +25,20 @@ def F():
 
 
 def _gpu_hough(F, img_np, split, schedule=None, quadrants=(0, 1, 2, 3)):
+    """Outputs of the plan's forward; integer images run twice, on one
+    workspace, and must repeat bit for bit (a race would show as a change)."""
     img = torch.from_numpy(np.ascontiguousarray(img_np)).cuda()
     plan = F.Plan(img.shape[0], img.shape[1], img.dtype, split, quadrants, schedule)
-    outs = plan.forward(img)
+    ws = plan.new_ws() if plan.ws_bytes else None
+    out = plan.new_out()
+    plan.forward(img, out, ws)
+    if img.dtype == torch.uint8:
+        again = torch.full_like(out, -7)
+        plan.forward(img, again, ws)
+        torch.cuda.synchronize()
+        assert torch.equal(out, again), "a second run differs"
     torch.cuda.synchronize()
-    return [o.cpu().numpy() for o in outs]
+    return [o.cpu().numpy() for o in plan.split_out(out)]
 
 
 def _assert_float_close(got, ref, absref, tol=1e-5):
