@@ -467,15 +467,19 @@ bool plan_axis(int W, int H, int split, const ElemRule &rule, const Schedule &sc
     do {
         int maxlv = (lin == 0) ? std::min(sched.first_levels, kMaxFirstLevels)
                                : std::min(sched.max_levels, kMaxSteps);
-        // A later pass takes one more level than the schedule asks for
+        // Later passes take one more level than the schedule asks for
         // wherever that saves a whole pass (an HBM round trip of every row):
-        // when the remaining levels r need fewer passes of m + 1 levels than
-        // of m (r = 4: 3 + 1 becomes 4; r = 7: 3 + 3 + 1 becomes 4 + 3).  The
-        // pass still takes fewer levels if the LDS budget requires it.
-        if (lin > 0) {
+        // the remaining r levels run in the fewest passes P of at most m + 1
+        // levels, and the last r - P m of them take m + 1 (r = 4: 3 + 1
+        // becomes 4; r = 7: 3 + 3 + 1 becomes 3 + 4).  The extra levels go to
+        // the last passes so that earlier passes keep narrow rows (16-bit
+        // pairs of uint8 images while nodes are at most 257 wide) as long as
+        // they can.  A pass still takes fewer levels if the LDS budget
+        // requires it.
+        if (lin > 0 && maxlv + 1 <= kMaxSteps) {
             const int r = L - lin;
-            if (maxlv + 1 <= kMaxSteps && (r + maxlv - 1) / maxlv > (r + maxlv) / (maxlv + 1))
-                ++maxlv;
+            const int P = (r + maxlv) / (maxlv + 1);
+            if (r - P * maxlv >= P) ++maxlv;  // every remaining pass needs m + 1
         }
         const int target = (lin == 0) ? sched.s_tile_first : sched.s_tile;
         bool found = false;

@@ -1,8 +1,8 @@
 """Full-element parity for the widest lane views.
 
-Plans of 2049 lanes and more run three fused passes (up to 8192 lanes: a
-later pass takes four tree levels where that saves a pass) or four (16384
-and 65536 lanes, up to the 65536 that fht_plan_create accepts); every
+Plans of 2049 lanes and more run three fused passes (up to 8192 lanes: the
+last later passes take four tree levels where that saves a pass) or four
+(16384 and 65536 lanes, up to the 65536 that fht_plan_create accepts); every
 output element is compared, not a sample: with classic Brady-Yong at
 4096 x 4096 (Sec. 3: both splits coincide with it at powers of two) and with
 the C oracle's direct sums elsewhere.  uint8 bit-exact (int32), float32

@@ -47,8 +47,8 @@ def test_tables_large_widths_sampled(split):
     # outputs of the interpreter with the C oracle.
     from oracle import native
     rng = np.random.default_rng(22)
-    # 300 and 4096 lanes: a later pass takes one level more than the
-    # schedule's three where that saves a pass (5 + 4 and 5 + 4 + 3 levels)
+    # 300 and 4096 lanes: the last later pass takes one level more than the
+    # schedule's three where that saves a pass (5 + 4 and 5 + 3 + 4 levels)
     for R, C in ((300, 9), (9, 257), (1021, 5), (4096, 3), (8191, 3)):
         img = rng.integers(0, 256, size=(R, C), dtype=np.uint8)
         h = F.fht_plan_create(R, C, F.FHT_U8, split, 15, None)
