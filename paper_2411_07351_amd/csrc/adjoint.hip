@@ -21,21 +21,24 @@ namespace fht {
 
 namespace {
 
-constexpr int kRowsPerBlock = 4;  // one wavefront per output row
+constexpr int kRowsPerBlock = 8;  // one wavefront per output row
 constexpr int kLoadsAtOnce = 32;  // loads of a wavefront in flight together
 
 // CH: 64-position chunks of a row per round of loads (4, or 8 for rows of
 // up to 512 positions, which then take one round instead of two); terms
-// whose loads are in flight together: kLoadsAtOnce / CH.
+// whose loads are in flight together: kLoadsAtOnce / CH.  The rows go in the
+// job's order: rows that read the same source rows (the descendants of one
+// node at the same relative slope) share a workgroup, and so its L1.
 template <typename T, int CH>
-__global__ void __launch_bounds__(256) adj_step_kernel(AdjArgs args)
+__global__ void __launch_bounds__(64 * kRowsPerBlock) adj_step_kernel(AdjArgs args)
 {
     constexpr int kTermsAtOnce = kLoadsAtOnce / CH;
     const AdjJob &job = args.job[blockIdx.y];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int x = blockIdx.x * kRowsPerBlock + wave;
-    if (x >= job.W) return;
+    const int slot = blockIdx.x * kRowsPerBlock + wave;
+    if (slot >= job.W) return;
+    const int x = job.order[slot];
     const int H = job.H;
     const int64_t b = blockIdx.z;  // image of a same-shape batch
     const T *src = reinterpret_cast<const T *>(static_cast<const char *>(job.src) + b * args.src_stride);
@@ -359,7 +362,8 @@ hipError_t launch_adjoint_step(Real real, const AdjArgs &args, int n_jobs, int m
                                hipStream_t stream, int n_images, int max_h)
 {
     if (n_jobs <= 0 || max_w <= 0 || n_images <= 0) return hipSuccess;
-    const dim3 grid((max_w + kRowsPerBlock - 1) / kRowsPerBlock, n_jobs, n_images), block(256);
+    const dim3 grid((max_w + kRowsPerBlock - 1) / kRowsPerBlock, n_jobs, n_images),
+        block(64 * kRowsPerBlock);
     const bool wide = max_h > 256;  // rows of 257..512 positions: one round of 8 chunks
     if (real == Real::F64) {
         if (wide) adj_step_kernel<double, 8><<<grid, block, 0, stream>>>(args);

@@ -67,6 +67,25 @@ constexpr int kNarrowWidth = 257;
 
 // Tree levels per adjoint gather launch.
 constexpr int kAdjointFuse = 3;
+
+// Output rows of a gather pass in the order its launch takes them, by the
+// lowest source row they read: the rows of a node's descendants (several
+// levels down) at the same relative slope read the same source rows at
+// different shifts, and consecutive rows of the order share a workgroup.
+std::vector<int32_t> gather_order(const fht::AdjointPass &ap)
+{
+    const int W = static_cast<int>(ap.offs.size()) - 1;
+    std::vector<int32_t> key(W), order(W);
+    for (int x = 0; x < W; ++x) {
+        int lo = INT32_MAX;
+        for (int i = ap.offs[x]; i < ap.offs[x + 1]; ++i) lo = std::min(lo, ap.terms[2 * i]);
+        key[x] = lo;
+        order[x] = x;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
+    return order;
+}
+
 // The fused final adjoint launch needs at least this many 64 x 64 tiles (one
 // per compute unit); below, the last gathers and the combine run apart.
 constexpr int64_t kFinalMinTiles = 256;
@@ -625,7 +644,7 @@ struct fht_plan_s {
             for (const fht::AdjointPass &ap : adjp[v]) {
                 adjp_offs[v].push_back(ob);
                 adjp_terms[v].push_back(tb);
-                ob += ap.offs.size();
+                ob += 2 * ap.offs.size() - 1;  // offsets, then the row order
                 tb += ap.terms.size() / 2;
             }
         }
@@ -650,6 +669,8 @@ struct fht_plan_s {
             std::vector<int32_t> offs, terms;
             for (const fht::AdjointPass &ap : adjp[v]) {
                 offs.insert(offs.end(), ap.offs.begin(), ap.offs.end());
+                const std::vector<int32_t> order = gather_order(ap);
+                offs.insert(offs.end(), order.begin(), order.end());
                 terms.insert(terms.end(), ap.terms.begin(), ap.terms.end());
             }
             e = upload(offs, &dt.adj_offs[v]);
@@ -1577,6 +1598,7 @@ fht_status fht_adjoint_many(fht_plan plan, int32_t n, const void *d_gouts, int64
                            : static_cast<const void *>(ws + plan->adj_ws_off[q][(k - 1) & 1]);
             j.dst = ws + plan->adj_ws_off[q][k & 1];
             j.offs = t->adj_offs[v] + plan->adjp_offs[v][k];
+            j.order = j.offs + ax.W + 1;
             j.terms = reinterpret_cast<const int2 *>(t->adj_terms[v]) + plan->adjp_terms[v][k];
             j.W = ax.W;
             j.H = (q >> 1) ? plan->R : plan->C;

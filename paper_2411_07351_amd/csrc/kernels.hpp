@@ -82,6 +82,7 @@ struct AdjJob {
     const void *src;       // [W][H] gradient rows in (the output gradient in pass 0)
     void *dst;             // [W][H] gradient rows out
     const int32_t *offs;   // W + 1 term offsets
+    const int32_t *order;  // the W output rows in launch order (a permutation of 0 .. W - 1)
     const int2 *terms;     // {source row, shift mod H}
     int32_t W, H;
     int32_t mirror_in;     // read src at mirrored positions (pass 0 of V-/H-)
