@@ -7,9 +7,11 @@ its four quadrant Hough images back, left on the device.  The loop:
    (``fht_planner``: C++ worker threads that also copy the plan's programs to
    the device, so the loop only submits and polls and never shares the GIL
    with planning), with an LRU cache of plans by shape, dtype and split;
-2. admits planned requests first come, first served, while their device
-   footprint (image, outputs, workspace and work-list tables) fits the HBM
-   budget; a request larger than the whole budget is rejected, not crashed;
+2. admits requests first come, first served once their plans are made (a
+   request whose plan is ready does not wait for an earlier one's), while
+   their device footprint (image, outputs, workspace and work-list tables)
+   fits the HBM budget; a request larger than the whole budget is rejected,
+   not crashed;
 3. whenever one of its launch slots (streams x depth) is free, launches the
    admitted requests of the oldest one's dtype (up to the batch limits) as one
    batch on that slot's stream: image uploads, the batch's tables and its
@@ -53,6 +55,10 @@ def _kind(image) -> str:
     if "float64" in name:
         return "f64"
     raise ValueError(f"unsupported image dtype {image.dtype}")
+
+
+# Pending plans the serving loop polls per round (oldest first).
+_POLL_WINDOW = 64
 
 
 @dataclass(eq=False)
@@ -392,22 +398,30 @@ class Server:
                 except ValueError as e:
                     self._finish(r, "rejected", now, str(e))
                 busy = True
-            # planned -> admission queue (in arrival order)
-            while planning and planning[0][1].done():
-                r, fut = planning.popleft()
-                busy = True
-                try:
-                    r.plan = fut.result()
-                except (B.FhtError, ValueError) as e:
-                    self._finish(r, "rejected", now, str(e))
-                    continue
-                r.t_planned = now
-                r.footprint = footprint(r.plan, r.kind)
-                if r.footprint > self.budget:
-                    self._finish(r, "rejected", now, "larger than the HBM budget")
-                    continue
-                r.status = "planned"
-                ready.append(r)
+            # planned -> admission queue, as plans complete (in arrival order
+            # among those completed together): a large plan still being made
+            # holds up no request behind it.  The oldest _POLL_WINDOW pending
+            # plans are polled per round.
+            if planning:
+                waiting = deque()
+                for i, (r, fut) in enumerate(planning):
+                    if i >= _POLL_WINDOW or not fut.done():
+                        waiting.append((r, fut))
+                        continue
+                    busy = True
+                    try:
+                        r.plan = fut.result()
+                    except (B.FhtError, ValueError) as e:
+                        self._finish(r, "rejected", now, str(e))
+                        continue
+                    r.t_planned = now
+                    r.footprint = footprint(r.plan, r.kind)
+                    if r.footprint > self.budget:
+                        self._finish(r, "rejected", now, "larger than the HBM budget")
+                        continue
+                    r.status = "planned"
+                    ready.append(r)
+                planning = waiting
             # completions
             for f in list(self.inflight):
                 if self.executor.done(f.handle):

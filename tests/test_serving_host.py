@@ -239,3 +239,53 @@ def test_fault_hook_of_the_c_abi():
     finally:
         F.fht_debug_fail_next(0, 0)
         F.fht_batch_destroy(b)
+
+
+class _HeldFirstPlans:
+    """Plan source whose first request's plan is finished only after every
+    other plan has been taken (a large plan still being made), or after 2000
+    polls (so that a loop that waited for it in arrival order ends too)."""
+
+    def __init__(self, n):
+        self.n, self.taken, self.calls, self.polls = n, 0, 0, 0
+
+    def get(self, rows, cols, kind, split):
+        first = self.calls == 0
+        self.calls += 1
+        src = self
+
+        class Fut:
+            def __init__(self):
+                self.plan = F.Plan(rows, cols, kind, split)
+
+            def done(self):
+                if first:
+                    src.polls += 1
+                return not first or src.taken >= src.n - 1 or src.polls > 2000
+
+            def result(self):
+                if not first:
+                    src.taken += 1
+                return self.plan
+
+        return Fut()
+
+    def close(self):
+        pass
+
+
+def test_a_plan_still_being_made_holds_up_no_later_request():
+    reqs = _requests(12, 1e9, seed=13)
+    for r in reqs:
+        r.arrival = 0.0
+    clock = FakeClock()
+    ex = FakeExecutor(clock)
+    srv = S.Server(ex, 1 << 40, clock=clock, plan_threads=1)
+    srv.plans.close()
+    srv.plans = _HeldFirstPlans(len(reqs))
+    srv.run(reqs)
+    assert all(r.status == "done" for r in reqs)
+    first = next(r for r in reqs if r.rid == 0)
+    # the other requests were planned, admitted and launched before request 0
+    assert all(r.t_launch <= first.t_launch for r in reqs)
+    assert 0 not in ex.launched[0]["rids"]
