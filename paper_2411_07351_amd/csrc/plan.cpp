@@ -127,7 +127,7 @@ struct PlanWork {
     std::map<std::pair<int, int>, std::vector<int32_t>> by_width;
     std::vector<const int32_t *> by_node;
     std::vector<Block> blocks;
-    std::vector<int> order;
+    std::vector<int> order, step_at;
     std::vector<Live> live;
 
     explicit PlanWork(const Tree &t) : tr(t), by_node(t.nodes.size(), nullptr) {}
@@ -183,18 +183,35 @@ struct TileBuilder {
     }
 };
 
+// The widest window (hi - lo) of the blocks TileBuilder::need would make for
+// rows [ulo, uhi] of node ni with window [lo, hi), without making them.
+int widest_window(const Tree &tr, PlanWork &work, int lin, int ni, int ulo, int uhi, int lo, int hi)
+{
+    const Node &n = tr.nodes[ni];
+    int w = hi - lo;
+    if (n.height <= lin) return w;
+    const int32_t *tt = work.rows(ni);
+    const int t0lo = tt[2 * ulo], t0hi = tt[2 * uhi];
+    const int t1lo = tt[2 * ulo + 1], t1hi = tt[2 * uhi + 1];
+    w = std::max(w, widest_window(tr, work, lin, n.left, t0lo, t0hi, lo, hi));
+    return std::max(w, widest_window(tr, work, lin, n.right, t1lo, t1hi, lo + (ulo - t1lo),
+                                     hi + (uhi - t1hi)));
+}
+
 // First-fit placement of the blocks in LDS; a block may reuse the space of
 // blocks whose last reader ran in an earlier step.  Returns the footprint.
 int place(std::vector<Block> &blocks, PlanWork &work)
 {
-    // blocks in step order, in index order within a step
+    // blocks in step order, in index order within a step (a counting sort)
     std::vector<int> &order = work.order;
-    order.clear();
     int max_step = 0;
     for (const Block &b : blocks) max_step = std::max(max_step, b.step);
-    for (int st = 0; st <= max_step; ++st)
-        for (size_t i = 0; i < blocks.size(); ++i)
-            if (blocks[i].step == st) order.push_back(static_cast<int>(i));
+    std::vector<int> &at = work.step_at;
+    at.assign(static_cast<size_t>(max_step) + 2, 0);
+    for (const Block &b : blocks) ++at[b.step + 1];
+    for (int st = 0; st <= max_step; ++st) at[st + 1] += at[st];
+    order.resize(blocks.size());
+    for (size_t i = 0; i < blocks.size(); ++i) order[at[blocks[i].step]++] = static_cast<int>(i);
     std::vector<Live> &live = work.live;  // kept in offset order
     live.clear();
     int top = 0;
@@ -371,8 +388,10 @@ void share_tile(Pass *pass, int src, int delta)
     pass->hdrs.insert(pass->hdrs.end(), hdr, hdr + kHdrInts);
 }
 
+// Stops early (the pass then fails the caller's checks) once a program
+// outgrows `max_lds` elements or the kernels' limits.
 void build_pass(const Tree &tr, PlanWork &work, int lin, int lout, int T, int S, int K,
-                int pad, int H, bool load_merge, Pass *pass)
+                int pad, int H, bool load_merge, int max_lds, Pass *pass)
 {
     pass->lin = lin;
     pass->lout = lout;
@@ -393,8 +412,12 @@ void build_pass(const Tree &tr, PlanWork &work, int lin, int lout, int T, int S,
         const std::array<int, 3> here{w, tr.nodes[r].a, prog0};
         for (int ta = 0, j = 0; ta < w; ta += tt, ++j) {
             const int prog = static_cast<int>(pass->hdrs.size() / kHdrInts);
-            if (same) share_tile(pass, (*same)[2] + j, here[1] - (*same)[1]);
-            else emit_tile(tr, work, r, ta, std::min(w, ta + tt), lin, S, K, pad, load_merge, pass);
+            if (same) {
+                share_tile(pass, (*same)[2] + j, here[1] - (*same)[1]);
+            } else {
+                emit_tile(tr, work, r, ta, std::min(w, ta + tt), lin, S, K, pad, load_merge, pass);
+                if (!pass->fits || pass->max_lds_elems > max_lds) return;
+            }
             for (int s0 = 0; s0 < H; s0 += S) {
                 pass->items.push_back(prog);
                 pass->items.push_back(0);
@@ -410,7 +433,7 @@ void build_pass(const Tree &tr, PlanWork &work, int lin, int lout, int T, int S,
 // fits the target width (windows are the tile plus a spread that depends on
 // the slope tile only).
 void build_pass_fitted(const Tree &tr, PlanWork &work, int lin, int lout, int T, int target,
-                       int pad, int H, bool load_merge, Pass *out)
+                       int pad, int H, bool load_merge, int max_lds, Pass *out)
 {
     // Windows are S plus a spread that does not depend on S (nor on K): take
     // the widest window of every tile for S = 16, then pick the largest S.
@@ -423,17 +446,13 @@ void build_pass_fitted(const Tree &tr, PlanWork &work, int lin, int lout, int T,
         if (std::find(seen.begin(), seen.end(), w) != seen.end()) continue;
         seen.push_back(w);
         const int tt = (T <= 0) ? w : T;
-        for (int ta = 0; ta < w; ta += tt) {
-            work.blocks.clear();
-            TileBuilder probe{tr, work, lin, 1, kChunk, work.blocks};
-            probe.need(r, ta, std::min(w, ta + tt) - 1, 0, 16);
-            for (const Block &b : probe.blocks) widest = std::max(widest, b.width());
-        }
+        for (int ta = 0; ta < w; ta += tt)
+            widest = std::max(widest, widest_window(tr, work, lin, r, ta, std::min(w, ta + tt) - 1, 0, 16));
     }
     const int spread = widest - 16;
     const int S = std::min(H, std::max(16, target - spread));
     const int K = std::max(1, chunks_of(S + spread));
-    build_pass(tr, work, lin, lout, T, S, K, pad, H, load_merge, out);
+    build_pass(tr, work, lin, lout, T, S, K, pad, H, load_merge, max_lds, out);
 }
 
 }  // namespace
@@ -507,7 +526,7 @@ bool plan_axis(int W, int H, int split, const ElemRule &rule, const Schedule &sc
             const bool load_merge = eb != 4;
             for (int T : tiles) {
                 Pass p;
-                build_pass_fitted(tr, work, lin, lout, T, target, pad, H, load_merge, &p);
+                build_pass_fitted(tr, work, lin, lout, T, target, pad, H, load_merge, budget_elems, &p);
                 p.elem_bytes = eb;
                 for (size_t h = 0; h < p.hdrs.size(); h += kHdrInts) p.hdrs[h + kHdrElemBytes] = eb;
                 if (p.fits && p.max_lds_elems <= budget_elems) {
