@@ -165,6 +165,7 @@ def _latency_config1(torch, F, WL, reps: int = 400):
     return {"workload": "one 61x47 uint8 image, 4 quadrants, FHT2DS, int32 outputs, "
                         f"{F.fht_plan_num_launches(plan.handle)} launches, each transform "
                         "launched alone and waited for",
+            "seed": WL.SEED_BASE + 1,
             "reps": reps,
             "gpu_ms": {"p50": pct(gpu, 50), "p99": pct(gpu, 99)},
             "host_ms": {"p50": pct(host, 50), "p99": pct(host, 99)}}
@@ -252,7 +253,9 @@ def _serving(args, torch, F, WL):
         "workload": f"{n} requests per run (a fresh set each run), sides log-uniform in "
                     "[64, 4096], 70% uint8 edge maps / 30% float32 N(0,1), Poisson arrivals, "
                     "4 quadrants, FHT2DS",
+        "seed": f"{WL.SEED_BASE} + 5 + 1000 k for run k (0: capacity, 1-3: the rates; 9: warm-up)",
         "mpixels": round(sum(r * c for r, c in shapes) / 1e6, 1),
+        "shape_histogram": _side_histogram(shapes),
         "u8_requests": sum(k == "u8" for k, _ in sets[0][0]),
         "hbm_budget_gb": budget / 1e9,
         "streams": 2, **{k: v for k, v in cfg.items() if k != "keep_outputs"},
@@ -320,6 +323,7 @@ def _differentiable(args, torch, F, WL):
     comp = COMPULSORY_BPP_F32_FWD_ADJ * px
     return {"workload": f"{n} float32 {R}x{C} N(0,1) images, forward + adjoint, 4 quadrants, "
                         "one launch per pass or level for the whole batch",
+            "seed": WL.SEED_BASE + 4,
             "value": round(px / (mfb_ms * 1e-3) / 1e6, 1), "unit": "Mpixel/s",
             "roofline": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBPS,
                          "compulsory_bytes": comp,
@@ -340,6 +344,15 @@ def _differentiable(args, torch, F, WL):
             # gathers fused with the sum into the image gradient)
             "adjoint_launches": max(1, max(F.fht_plan_adjoint_num_passes(plan.handle, v)
                                            for v in (0, 1)))}
+
+
+def _side_histogram(shapes) -> dict:
+    """Images per octave of their larger side, e.g. {"<=64": 12, "<=128": 40, ...}."""
+    hist = {}
+    for r, c in shapes:
+        k = 1 << max(0, (max(r, c) - 1).bit_length())
+        hist[k] = hist.get(k, 0) + 1
+    return {f"<={k}": hist[k] for k in sorted(hist)}
 
 
 def _ragged_tuned(args, torch, F, shapes, rimgs, routs, rpx, stream):
@@ -490,7 +503,7 @@ def main():
             "workload": f"{n} x {R}x{C} uint8 edge maps (Bernoulli 0.05 + 20 segments), "
                         f"4 quadrants, FHT2D{args.split}, int32 outputs, plain per-image launches",
             "images": n, "rows": R, "cols": C, "split": args.split, "path": "plain",
-            "launches_per_image": nl,
+            "launches_per_image": nl, "seed": WL.SEED_BASE + 2,
         },
         "effective_gbps": round(COMPULSORY_BPP * px_per_step * args.steps / plain_s / 1e9, 1),
         "frac_compulsory": round(COMPULSORY_BPP * px_per_step * args.steps / plain_s / 1e9 /
@@ -609,7 +622,9 @@ def main():
         result["ragged"] = {
             "workload": f"{args.ragged} uint8 edge maps, sides log-uniform in [32, 2048], "
                         "4 quadrants, int32 outputs",
+            "seed": WL.SEED_BASE + 3,
             "mpixels": round(rpx / 1e6, 2),
+            "shape_histogram": _side_histogram(shapes),
             "batched": {"value": round(rpx / (rbms * 1e-3) / 1e6, 1), "unit": "Mpixel/s",
                         "ms_per_step": round(rbms, 3), "graph": True,
                         "launches": rb.num_launches, "schedule": "library default"},
