@@ -108,3 +108,42 @@ def test_plan_addition_count_equals_theorem1_count(split):
         expect = 2 * O.additions(R, sp, C) + 2 * O.additions(C, sp, R)
         assert w["adds_tree"] == expect, (R, C)
         assert w["adds_executed"] >= expect
+
+
+def test_random_schedules_and_shapes():
+    # Seeded fuzz over the schedule's knobs (within their documented ranges)
+    # and shapes, both splits, uint8 and float element rules: every plan that
+    # is accepted runs in the interpreter (which checks the kernel's
+    # invariants: bounds, no read-after-write inside a step, single writes)
+    # and equals the oracle.
+    rng = np.random.default_rng(23)
+    accepted = 0
+    for _ in range(48):
+        sched = dict(s_tile=int(rng.choice([64, 128, 192, 256])),
+                     s_tile_first=int(rng.choice([64, 128, 192, 256])),
+                     first_levels=int(rng.integers(1, 7)), max_levels=int(rng.integers(1, 9)),
+                     lds_budget=int(rng.choice([4096, 16384, 65536, 98304])),
+                     t_tile=int(rng.choice([0, 4, 8, 16, 32])),
+                     threads=int(rng.choice([256, 512])), threads_first=int(rng.choice([256, 512])))
+        R, C = (int(v) for v in np.exp(rng.uniform(0, np.log(600), size=2)))
+        C = min(C, 40)  # positions: keep the interpreter quick
+        split = int(rng.integers(0, 2))
+        kind = [F.FHT_U8, F.FHT_F32][int(rng.integers(0, 2))]
+        try:
+            h = F.fht_plan_create(R, C, kind, split, 15, F.fht_schedule(**sched))
+        except F.FhtError:
+            continue  # no pass fits this budget: rejected, not mis-planned
+        accepted += 1
+        try:
+            if kind == F.FHT_U8:
+                img = rng.integers(0, 256, size=(R, C), dtype=np.uint8)
+                ref = O.hough4(img, split)
+            else:
+                img = rng.integers(-8, 9, size=(R, C)).astype(np.float32)
+                ref = O.hough4(img.astype(np.int64), split)
+            for q in range(4):
+                got = run_plan_tables(h, img, q)
+                assert (got == ref[q]).all(), (R, C, split, kind, sched, q)
+        finally:
+            F.fht_plan_destroy(h)
+    assert accepted >= 32
