@@ -1702,6 +1702,7 @@ fht_status fht_peaks(fht_plan plan, const void *d_out, int32_t k, int32_t radius
     a.capacity = capacity;
     a.counter = static_cast<uint32_t *>(d_ws);
     a.keys = reinterpret_cast<uint64_t *>(static_cast<char *>(d_ws) + 256);
+    a.flat = d_out;
     a.out = reinterpret_cast<fht::PeakOut *>(d_peaks);
     a.n_found = d_found;
     const fht::PeakElem elem = plan->dtype == FHT_U8    ? fht::PeakElem::I32

@@ -145,7 +145,8 @@ struct PeakArgs {
     double min_value;
     int32_t k, capacity;
     uint32_t *counter;             // workspace: candidate count
-    uint64_t *keys;                // workspace: candidate keys (quadrant slot << 48 | index)
+    uint64_t *keys;                // workspace: candidate keys (flat output index)
+    const void *flat;              // the whole output (flat index 0)
     PeakOut *out;                  // k peaks, strongest first
     int32_t *n_found;              // [0] peaks written, [1] candidates found
 };

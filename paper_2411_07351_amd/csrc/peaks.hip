@@ -11,11 +11,9 @@ namespace fht {
 
 namespace {
 
-// A candidate's key is its quadrant slot (bits 48..) and its index in that
-// quadrant: quadrants are stored in q order, so keys order candidates by their
-// flat output index.
+// A candidate's key is its flat output index (quadrants are stored in q
+// order, so keys order candidates by quadrant, then slope, then shift).
 constexpr uint64_t kNoKey = ~0ull;
-constexpr int kKeySlotShift = 48;
 
 __global__ void peaks_clear_kernel(uint32_t *counter) { if (threadIdx.x == 0) counter[0] = 0; }
 
@@ -49,16 +47,7 @@ __global__ void __launch_bounds__(256) peaks_nms_kernel(PeakArgs a)
     }
     const uint32_t slot = atomicAdd(a.counter, 1u);
     if (slot < static_cast<uint32_t>(a.capacity))
-        a.keys[slot] = (static_cast<uint64_t>(qi) << kKeySlotShift) | e;
-}
-
-template <typename T>
-__device__ __forceinline__ double key_value(const PeakArgs &a, uint64_t key)
-{
-    const int qi = static_cast<int>(key >> kKeySlotShift);
-    const size_t e = key & ((1ull << kKeySlotShift) - 1);
-    const void *src = qi == 0 ? a.src[0] : qi == 1 ? a.src[1] : qi == 2 ? a.src[2] : a.src[3];
-    return static_cast<double>(static_cast<const T *>(src)[e]);
+        a.keys[slot] = a.base[qi] + e;
 }
 
 // (value, key) beats (bv, bk): larger value, then smaller flat index.  Every
@@ -69,72 +58,210 @@ __device__ __forceinline__ bool beats(double v, uint64_t k, double bv, uint64_t 
 }
 
 constexpr int kSelThreads = 1024;
+constexpr int kSortCap = 8192;  // candidates sorted in LDS at once (k <= 4096 of them wanted)
+
+// Order-preserving 64-bit image of a value (larger value, larger image; -0
+// and +0 are one value, as in the comparison above).
+__device__ __forceinline__ uint64_t ordered(double v)
+{
+    if (v == 0.0) v = 0.0;
+    const uint64_t b = static_cast<uint64_t>(__double_as_longlong(v));
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__device__ __forceinline__ bool before(uint64_t va, uint64_t ka, uint64_t vb, uint64_t kb)
+{
+    return va > vb || (va == vb && ka < kb);
+}
+
+// The selection's view of the arguments, in scalars: a candidate's quadrant
+// slot follows from comparing its key with the slots' first flat indices
+// (slots past the last present one start at the largest key), never from
+// indexing the argument arrays by a per-lane slot, which would copy them to
+// scratch memory.
+template <typename T>
+struct SelView {
+    const T *flat;
+    uint64_t b0, b1, b2, b3;
+    int h0, h1, h2, h3, q0, q1, q2, q3;
+
+    __device__ explicit SelView(const PeakArgs &a)
+        : flat(static_cast<const T *>(a.flat)), b0(a.base[0]),
+          b1(a.nq > 1 ? a.base[1] : kNoKey), b2(a.nq > 2 ? a.base[2] : kNoKey),
+          b3(a.nq > 3 ? a.base[3] : kNoKey), h0(a.H[0]), h1(a.H[1]), h2(a.H[2]), h3(a.H[3]),
+          q0(a.quadrant[0]), q1(a.quadrant[1]), q2(a.quadrant[2]), q3(a.quadrant[3]) {}
+
+    __device__ __forceinline__ double value(uint64_t key) const
+    {
+        return static_cast<double>(flat[key]);
+    }
+
+    // Slot s holds the keys from b_s on, and b1 <= b2 <= b3: a key at or past
+    // b3 is past b2 and b1 too, so the fields follow by adding differences
+    // (a chain of selects would become an indexed load of this object).
+    __device__ __forceinline__ PeakOut peak(uint64_t key, double v) const
+    {
+        const int i1 = key >= b1, i2 = key >= b2, i3 = key >= b3;
+        const uint64_t base = b0 + i1 * (b1 - b0) + i2 * (b2 - b1) + i3 * (b3 - b2);
+        const uint64_t e = key - base;
+        const int H = h0 + i1 * (h1 - h0) + i2 * (h2 - h1) + i3 * (h3 - h2);
+        PeakOut p;
+        p.value = static_cast<float>(v);
+        p.quadrant = q0 + i1 * (q1 - q0) + i2 * (q2 - q1) + i3 * (q3 - q2);
+        p.t = static_cast<int32_t>(e / H);
+        p.s = static_cast<int32_t>(e % H);
+        return p;
+    }
+};
 
 // The k strongest candidates (value descending, then flat output index
-// ascending) by k rounds of a workgroup argmax; each round removes its
-// winner.
+// ascending).  At most kSortCap candidates: all of them are sorted in LDS
+// (bitonic).  More: a radix select over the values' ordered images (8 bits
+// a round) finds the k-th largest value first, and only the candidates at or
+// above it are sorted; if those are still too many (a tie at that value
+// spanning thousands of candidates), k rounds of a workgroup argmax, each
+// removing its winner, pick them instead.
 template <typename T>
 __global__ void __launch_bounds__(kSelThreads) peaks_select_kernel(PeakArgs a)
 {
+    __shared__ uint64_t sv[kSortCap], sk[kSortCap];
+    __shared__ uint32_t hist[256];
+    __shared__ uint64_t sh_prefix, sh_mask;
+    __shared__ uint32_t sh_kk, sh_count;
     __shared__ double best_v[kSelThreads / 64];
     __shared__ uint64_t best_k[kSelThreads / 64];
     const uint32_t total = a.counter[0];
     const int m = static_cast<int>(min(total, static_cast<uint32_t>(a.capacity)));
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int found = 0;
-    for (int round = 0; round < a.k; ++round) {
-        double bv = 0.0;
-        uint64_t bk = kNoKey;
-        for (int i = threadIdx.x; i < m; i += kSelThreads) {
-            const uint64_t k = a.keys[i];
-            if (k == kNoKey) continue;
-            const double v = key_value<T>(a, k);
-            if (beats(v, k, bv, bk)) {
-                bv = v;
-                bk = k;
+    const int k = min(a.k, m);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const SelView<T> view(a);
+    uint64_t *keys = a.keys;
+    PeakOut *out = a.out;
+
+    // threshold: the ordered value of the k-th largest candidate (every
+    // candidate when they all fit)
+    uint64_t thr = 0;
+    if (m > kSortCap) {
+        if (tid == 0) {
+            sh_prefix = 0;
+            sh_mask = 0;
+            sh_kk = static_cast<uint32_t>(k);
+        }
+        for (int shift = 56; shift >= 0; shift -= 8) {
+            for (int b = tid; b < 256; b += kSelThreads) hist[b] = 0;
+            __syncthreads();
+            const uint64_t prefix = sh_prefix, mask = sh_mask;
+            for (int i = tid; i < m; i += kSelThreads) {
+                const uint64_t ov = ordered(view.value(keys[i]));
+                if ((ov & mask) == prefix) atomicAdd(&hist[(ov >> shift) & 255], 1u);
             }
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            const double ov = __shfl_xor(bv, off, 64);
-            const uint64_t ok = __shfl_xor(bk, off, 64);
-            if (ok != kNoKey && beats(ov, ok, bv, bk)) {
-                bv = ov;
-                bk = ok;
+            __syncthreads();
+            if (tid == 0) {
+                uint32_t kk = sh_kk;
+                for (int b = 255; b >= 0; --b) {
+                    if (kk <= hist[b]) {
+                        sh_prefix = prefix | (static_cast<uint64_t>(b) << shift);
+                        sh_mask = mask | (0xffull << shift);
+                        break;
+                    }
+                    kk -= hist[b];
+                }
+                sh_kk = kk;
             }
+            __syncthreads();
         }
-        if (lane == 0) {
-            best_v[wave] = bv;
-            best_k[wave] = bk;
-        }
-        __syncthreads();
-        double tv = 0.0;
-        uint64_t tk = kNoKey;
-        for (int w = 0; w < kSelThreads / 64; ++w)
-            if (best_k[w] != kNoKey && beats(best_v[w], best_k[w], tv, tk)) {
-                tv = best_v[w];
-                tk = best_k[w];
-            }
-        __syncthreads();
-        if (tk == kNoKey) break;
-        // remove the winner (keys are unique: they hold the output index)
-        for (int i = threadIdx.x; i < m; i += kSelThreads)
-            if (a.keys[i] == tk) a.keys[i] = kNoKey;
-        if (threadIdx.x == 0) {
-            const int qi = static_cast<int>(tk >> kKeySlotShift);
-            const uint64_t e = tk & ((1ull << kKeySlotShift) - 1);
-            const int H = qi == 0 ? a.H[0] : qi == 1 ? a.H[1] : qi == 2 ? a.H[2] : a.H[3];
-            PeakOut p;
-            p.value = static_cast<float>(tv);
-            p.quadrant = qi == 0 ? a.quadrant[0] : qi == 1 ? a.quadrant[1]
-                       : qi == 2 ? a.quadrant[2] : a.quadrant[3];
-            p.t = static_cast<int32_t>(e / H);
-            p.s = static_cast<int32_t>(e % H);
-            a.out[round] = p;
-        }
-        ++found;
-        __syncthreads();
+        thr = sh_prefix;
     }
-    if (threadIdx.x == 0) {
+    // collect the candidates at or above the threshold
+    if (tid == 0) sh_count = 0;
+    __syncthreads();
+    for (int i = tid; i < m; i += kSelThreads) {
+        const uint64_t key = keys[i];
+        const uint64_t ov = ordered(view.value(key));
+        if (ov >= thr) {
+            const uint32_t slot = atomicAdd(&sh_count, 1u);
+            if (slot < static_cast<uint32_t>(kSortCap)) {
+                sv[slot] = ov;
+                sk[slot] = key;
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t got = sh_count;
+    int found = 0;
+    if (got <= static_cast<uint32_t>(kSortCap)) {
+        // bitonic sort of the collected candidates, padded to a power of two
+        // with entries that sort last
+        int n = 1;
+        while (n < static_cast<int>(got)) n <<= 1;
+        for (int i = static_cast<int>(got) + tid; i < n; i += kSelThreads) {
+            sv[i] = 0;
+            sk[i] = kNoKey;
+        }
+        __syncthreads();
+        for (int size = 2; size <= n; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int i = tid; i < n / 2; i += kSelThreads) {
+                    const int lo = 2 * i - (i & (stride - 1)), hi = lo + stride;
+                    const bool up = (lo & size) == 0;
+                    const uint64_t vl = sv[lo], kl = sk[lo], vh = sv[hi], kh = sk[hi];
+                    if (before(vh, kh, vl, kl) == up) {
+                        sv[lo] = vh;
+                        sk[lo] = kh;
+                        sv[hi] = vl;
+                        sk[hi] = kl;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int i = tid; i < k; i += kSelThreads) out[i] = view.peak(sk[i], view.value(sk[i]));
+        found = k;
+    } else {
+        for (int round = 0; round < k; ++round) {
+            double bv = 0.0;
+            uint64_t bk = kNoKey;
+            for (int i = tid; i < m; i += kSelThreads) {
+                const uint64_t kx = keys[i];
+                if (kx == kNoKey) continue;
+                const double v = view.value(kx);
+                if (beats(v, kx, bv, bk)) {
+                    bv = v;
+                    bk = kx;
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ov = __shfl_xor(bv, off, 64);
+                const uint64_t ok = __shfl_xor(bk, off, 64);
+                if (ok != kNoKey && beats(ov, ok, bv, bk)) {
+                    bv = ov;
+                    bk = ok;
+                }
+            }
+            if (lane == 0) {
+                best_v[wave] = bv;
+                best_k[wave] = bk;
+            }
+            __syncthreads();
+            double tv = 0.0;
+            uint64_t tk = kNoKey;
+            for (int w = 0; w < kSelThreads / 64; ++w)
+                if (best_k[w] != kNoKey && beats(best_v[w], best_k[w], tv, tk)) {
+                    tv = best_v[w];
+                    tk = best_k[w];
+                }
+            __syncthreads();
+            if (tk == kNoKey) break;
+            // remove the winner (keys are unique: they hold the output index)
+            for (int i = tid; i < m; i += kSelThreads)
+                if (keys[i] == tk) keys[i] = kNoKey;
+            if (tid == 0) out[round] = view.peak(tk, tv);
+            ++found;
+            __syncthreads();
+        }
+    }
+    if (tid == 0) {
         a.n_found[0] = found;
         a.n_found[1] = static_cast<int32_t>(min(total, 0x7fffffffu));
     }

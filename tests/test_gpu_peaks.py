@@ -37,6 +37,30 @@ def test_peaks_equal_reference(case):
     assert _as_list(recs) == ref
 
 
+@pytest.mark.parametrize("case", [
+    # radius 0: every output above the floor is a candidate.  65536 of them:
+    # more than the selection sorts at once, so the k-th largest value is
+    # found by a radix select first (ties at it included in the sort)
+    ("u8", 128, 128, 0, 4096, 0.0),
+    # all outputs equal: the tie at the k-th value spans every candidate,
+    # which the selection then takes in rounds
+    ("zero", 61, 47, 0, 100, 0.0),
+    # a few thousand candidates, k at its limit
+    ("u8", 100, 90, 1, 4096, 0.0),
+])
+def test_peaks_many_candidates(case):
+    kind, R, C, radius, k, floor = case
+    rng = WL.rng_for(1, salt=40 + R)
+    img = np.zeros((R, C), dtype=np.uint8) if kind == "zero" else WL.uniform_u8(rng, R, C)
+    plan = F.Plan(R, C, "u8", "S")
+    out = plan.new_out("cuda")
+    plan.forward(torch.from_numpy(img).cuda(), out)
+    recs, cands = plan.peaks(out, k=k, radius=radius, min_value=floor, capacity=1 << 17)
+    ref, ref_cands = local_maxima_topk(_outs(plan, out.cpu().numpy()), k, radius, floor)
+    assert cands == ref_cands
+    assert _as_list(recs) == ref
+
+
 def test_peaks_f64_order_by_exact_value():
     # float64 outputs that round to the same float32 must still be ordered by
     # their own values: integer pixels plus a perturbation far below float32
