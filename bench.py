@@ -138,6 +138,43 @@ def _cpu_alg1(imgs_np, split: int, budget_s: float):
             "cpu_model": cpu_model()}
 
 
+def _peaks(torch, F, WL):
+    """Peak finding after the transform (device time of the fht_peaks call,
+    events around it): the planted segments of a 1021 x 1021 edge map, and
+    k = 4096 peaks of a uniform 1021 x 1021 image (about 137 000 candidates)."""
+    import numpy as np
+    res = {}
+    for name, kind, k, radius, floor in (("edge_map_1021_k80_r8", "edge", 80, 8, 120.0),
+                                         ("uniform_1021_k4096_r2", "u8", 4096, 2, 0.0)):
+        rng = WL.rng_for(2, salt=50)
+        img = WL.edge_map(rng, 1021, 1021) if kind == "edge" else WL.uniform_u8(rng, 1021, 1021)
+        plan = F.Plan(1021, 1021, "u8", "S")
+        out = plan.new_out("cuda")
+        plan.forward(torch.from_numpy(np.ascontiguousarray(img)).cuda(), out)
+        cap = 1 << 20
+        ws = torch.empty(F.fht_peaks_workspace_bytes(cap), dtype=torch.uint8, device="cuda")
+        rec = torch.empty(k * F.PEAK_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        found = torch.zeros(2, dtype=torch.int32, device="cuda")
+        sh = torch.cuda.current_stream().cuda_stream
+
+        def call():
+            F.fht_peaks(plan.handle, out.data_ptr(), k, radius, floor, cap, ws.data_ptr(),
+                        rec.data_ptr(), found.data_ptr(), sh)
+
+        call()
+        torch.cuda.synchronize()
+        a, b = _events(torch)
+        a.record()
+        for _ in range(5):
+            call()
+        b.record()
+        torch.cuda.synchronize()
+        n, cands = (int(v) for v in found.cpu())
+        res[name] = {"ms": round(a.elapsed_time(b) / 5, 4), "k": k, "radius": radius,
+                     "peaks": n, "candidates": cands}
+    return res
+
+
 def _latency_config1(torch, F, WL, reps: int = 400):
     """One 61 x 47 uint8 image (the smallest workload): latency of single
     transforms, each launched alone and waited for."""
@@ -655,6 +692,7 @@ def main():
         result["copy_calibration_bytes"] = 2 * (args.copy_mib << 20)
 
     result["latency_61x47"] = _latency_config1(torch, F, WL)
+    result["peaks"] = _peaks(torch, F, WL)
     if args.ragged > 0 and args.tune:
         result["ragged"]["batched_tuned"] = _ragged_tuned(args, torch, F, *tune_leg, stream)
         del tune_leg
