@@ -4,8 +4,10 @@
 Headline workload (one "step"): 64 uint8 edge maps of 1021 x 1021
 (Bernoulli(0.05) background plus 20 Bresenham segments, seed 2411_07351 + 2),
 all four quadrant Hough images with int32 outputs, FHT2DS split, launched per
-image (``fht_forward_launch`` for every fused pass of every image).  The same
-batch also runs batched (one launch per fused pass for all 64 images,
+image (``fht_forward_launch`` for every fused pass of every image), with the
+schedule for per-image launches that the tuner picks on this workload (the
+library default or a two-pass schedule; both timings are reported).  The same
+batch also runs batched (library default schedule) (one launch per fused pass for all 64 images,
 replayed from a captured HIP graph), and a ragged batch of 512 edge maps with
 sides log-uniform in [32, 2048] runs both ways.  Inputs are resident in HBM
 before timing starts.
@@ -58,6 +60,8 @@ def _parse():
                     help="also measure torch's fill/copy/sum rates (1) or not (0)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a device copy of this many MiB (counter calibration)")
+    ap.add_argument("--plain-schedule", default="auto", choices=["auto", "default", "two-pass"],
+                    help="schedule of the per-image launches: picked by timing both (auto) or fixed")
     return ap.parse_args()
 
 
@@ -69,10 +73,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel: str, batched: bool = False):
+def _traffic(kernel: str, batched: bool = False, plain_schedule: str = "default"):
     """HBM bytes per launch of `kernel` from the committed counter summary, if it
     was taken on the current kernel sources (else None); `batched`: per launch
-    of the 64-image batch."""
+    of the 64-image batch, else per launch of the per-image path, which must
+    have run the schedule the summary was taken with."""
     try:
         vals = {}
         with open(TRAFFIC_FILE) as fh:
@@ -84,6 +89,8 @@ def _traffic(kernel: str, batched: bool = False):
     except OSError:
         return None
     if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    if not batched and vals.get("plain_schedule") != plain_schedule:
         return None
     key = "batched_bytes_per_launch" if batched else "bytes_per_launch"
     v = vals.get(f"{key}[{kernel}]")
@@ -470,18 +477,28 @@ def main():
 
     imgs_np = WL.edge_maps(WL.rng_for(2), n, R, C)
     imgs = torch.from_numpy(imgs_np).to(dev)
-    plan = F.Plan(R, C, "u8", split)
+    plan = F.Plan(R, C, "u8", split)  # the batched legs: library default schedule
     outs = torch.empty((n, plan.out_elems), dtype=torch.int32, device=dev)
-    ws = plan.new_ws(dev)
-    nl = F.fht_plan_num_launches(plan.handle)
-    info = [F.fht_plan_launch_info(plan.handle, l) for l in range(nl)]
     px_per_step = n * R * C
+
+    # The per-image launches' schedule (untimed): each candidate transforms
+    # 16 of the images, and they must agree on every output.
+    from paper_2411_07351_amd import tuning as T
+    if args.plain_schedule == "auto":
+        pname, ptimes = T.tune_plain([imgs[i] for i in range(min(n, 16))], args.split)
+    else:
+        pname, ptimes = args.plain_schedule, None
+    psched = T.PLAIN_SCHEDULES[pname]
+    pplan = F.Plan(R, C, "u8", split, schedule=psched) if psched else plan
+    ws = pplan.new_ws(dev)
+    nl = F.fht_plan_num_launches(pplan.handle)
+    info = [F.fht_plan_launch_info(pplan.handle, l) for l in range(nl)]
 
     def plain_step():
         for i in range(n):
             ip, op = imgs[i].data_ptr(), outs[i].data_ptr()
             for l in range(nl):
-                F.fht_forward_launch(plan.handle, l, ip, op, ws.data_ptr(), sh)
+                F.fht_forward_launch(pplan.handle, l, ip, op, ws.data_ptr(), sh)
 
     for _ in range(args.warmup):
         plain_step()
@@ -510,7 +527,7 @@ def main():
             e = _events(torch)
             e[0].record(stream)
             for i in range(n):
-                F.fht_forward_launch(plan.handle, l, imgs[i].data_ptr(), outs[i].data_ptr(),
+                F.fht_forward_launch(pplan.handle, l, imgs[i].data_ptr(), outs[i].data_ptr(),
                                      ws.data_ptr(), sh)
             e[1].record(stream)
             events[l].append(e)
@@ -519,8 +536,8 @@ def main():
     dom = int(np.argmax(launch_ms))
     dom_bytes = info[dom]["bytes_in"] + info[dom]["bytes_out"]
     achieved = dom_bytes / (launch_ms[dom] * 1e-3) / 1e9
-    dom_kernel = F.fht_plan_launch_kernel(plan.handle, dom)
-    traffic = _traffic(dom_kernel)
+    dom_kernel = F.fht_plan_launch_kernel(pplan.handle, dom)
+    traffic = _traffic(dom_kernel, plain_schedule=pname)
 
     value = px_per_step * args.steps / plain_s / 1e6
     result = {
@@ -541,7 +558,9 @@ def main():
                         f"4 quadrants, FHT2D{args.split}, int32 outputs, plain per-image launches",
             "images": n, "rows": R, "cols": C, "split": args.split, "path": "plain",
             "launches_per_image": nl, "seed": WL.SEED_BASE + 2,
+            "plain_schedule": pname, "plain_schedule_knobs": psched or "library default",
         },
+        "plain_schedule_us_per_image": ptimes,
         "effective_gbps": round(COMPULSORY_BPP * px_per_step * args.steps / plain_s / 1e9, 1),
         "frac_compulsory": round(COMPULSORY_BPP * px_per_step * args.steps / plain_s / 1e9 /
                                  HBM_PEAK_GBPS, 4),
@@ -564,7 +583,7 @@ def main():
             "avg_launch_us": round(launch_ms[dom] * 1e3, 2),
             "launch_avg_us": [round(m * 1e3, 2) for m in launch_ms],
             "launch_bytes": [i["bytes_in"] + i["bytes_out"] for i in info],
-            "launch_kernels": [F.fht_plan_launch_kernel(plan.handle, l) for l in range(nl)],
+            "launch_kernels": [F.fht_plan_launch_kernel(pplan.handle, l) for l in range(nl)],
             "kernel_source_hash": kernel_source_hash(),
         },
     }
@@ -593,7 +612,9 @@ def main():
             per[l].append(e)
     torch.cuda.synchronize()
     per_ms = [float(np.median([x.elapsed_time(y) for x, y in ev])) for ev in per]
-    lbytes = [n * (i["bytes_in"] + i["bytes_out"]) for i in info]
+    binfo = [F.fht_plan_launch_info(plan.handle, l)
+             for l in range(F.fht_plan_num_launches(plan.handle))]
+    lbytes = [n * (i["bytes_in"] + i["bytes_out"]) for i in binfo]
     result["batched"] = {
         "value": round(px_per_step / (bms * 1e-3) / 1e6, 1),
         "unit": "Mpixel/s",
@@ -608,7 +629,8 @@ def main():
         "path_gbps": round(sum(lbytes) / (bms * 1e-3) / 1e9, 1),
         "path_frac": round(sum(lbytes) / (bms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
     }
-    traf = [_traffic(F.fht_plan_launch_kernel(plan.handle, l), batched=True) for l in range(nl)]
+    traf = [_traffic(F.fht_plan_launch_kernel(plan.handle, l), batched=True)
+            for l in range(len(binfo))]
     if all(t is not None for t in traf):
         result["batched"]["launch_traffic_bytes"] = [round(t, 0) for t in traf]
         result["batched"]["traffic_gbps"] = round(sum(traf) / (bms * 1e-3) / 1e9, 1)

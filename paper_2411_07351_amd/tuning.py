@@ -267,6 +267,56 @@ def autotune(imgs, split="S", knobs=KNOBS, reps: int = 3, use_cache: bool = True
     return out
 
 
+# Schedules for images transformed one at a time (one launch per fused pass
+# per image).  Such launches hold at most a few rounds of work items, so each
+# costs about one item's latency plus the launch; fewer passes can then win
+# even where they lose in a batch.  "two-pass": a 6-level first pass and
+# 4-level later passes in up to 160 KB of LDS per item (10 levels, up to 1024
+# lanes per view, in two passes instead of three).
+PLAIN_SCHEDULES = {
+    "default": None,
+    "two-pass": dict(first_levels=6, max_levels=4, lds_budget=163840),
+}
+
+
+def tune_plain(imgs, split="S", candidates=("default", "two-pass"), reps: int = 3):
+    """Picks the schedule for per-image launches of same-shape `imgs` (device
+    tensors): each candidate of PLAIN_SCHEDULES transforms every image with
+    its own launches (device events, best of `reps` runs); the fastest wins.
+    Candidates must agree on every output (a schedule never changes the
+    result), else this raises.  Returns (name, {name: microseconds per image})."""
+    import torch
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+    R, C = imgs[0].shape
+    times, ref = {}, None
+    for name in candidates:
+        plan = B.Plan(R, C, imgs[0].dtype, _split_name(split), schedule=PLAIN_SCHEDULES[name])
+        outs = [plan.new_out(imgs[0].device) for _ in imgs]
+        ws = plan.new_ws(imgs[0].device)
+
+        def run():
+            for im, o in zip(imgs, outs):
+                B.fht_forward(plan.handle, im.data_ptr(), o.data_ptr(), ws.data_ptr(), sh)
+
+        run()
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = outs
+        elif not all(torch.equal(a, b) for a, b in zip(ref, outs)):
+            raise RuntimeError(f"schedule {name!r} changed the transform's result")
+        best = float("inf")
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            run()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) * 1e3 / len(imgs))
+        times[name] = round(best, 2)
+    return min(times, key=times.get), times
+
+
 def plans_for(shapes: Sequence[tuple], dtype, split="S", schedules: dict | None = None):
     """One plan per shape (shared between equal shapes), each with its size
     class's schedule from `schedules` (as autotune returns) or the cache, the

@@ -1,8 +1,9 @@
 """Parity at the benchmark's full sizes, in the launch configurations bench.py
-times: every image of the 64 x 1021x1021 batch and of the 512-image ragged
-batch (graph replays), and requests of the serving stream up to 4096 per
-side, checked on sampled outputs that the C oracle computes one by one
-(bit-exact for uint8, 1e-5 of the line's absolute sum for float32)."""
+times: every image of the 64 x 1021x1021 batch (graph replays, and per-image
+launches under both per-image schedules), every image of the 512-image ragged
+batch, and requests of the serving stream up to 4096 per side, checked on
+sampled outputs that the C oracle computes one by one (bit-exact for uint8,
+1e-5 of the line's absolute sum for float32)."""
 import numpy as np
 import pytest
 import torch
@@ -67,6 +68,32 @@ def test_bench_batch_64x1021_graph_every_image():
     plan.forward(imgs[5], solo)
     torch.cuda.synchronize()
     assert torch.equal(solo, outs[5])
+
+
+def test_bench_plain_schedules_64x1021_every_image():
+    # the per-image launches bench.py times, under both of its schedules
+    from paper_2411_07351_amd import tuning as T
+    n, R, C = 64, 1021, 1021
+    imgs_np = WL.edge_maps(WL.rng_for(2), n, R, C)
+    imgs = torch.from_numpy(imgs_np).cuda()
+    got = {}
+    for name, sched in T.PLAIN_SCHEDULES.items():
+        plan = F.Plan(R, C, "u8", "S", schedule=sched)
+        outs = torch.full((n, plan.out_elems), -1, dtype=torch.int32, device="cuda")
+        ws = plan.new_ws("cuda")
+        sh = torch.cuda.current_stream().cuda_stream
+        for i in range(n):
+            for l in range(F.fht_plan_num_launches(plan.handle)):
+                F.fht_forward_launch(plan.handle, l, imgs[i].data_ptr(), outs[i].data_ptr(),
+                                     ws.data_ptr(), sh)
+        torch.cuda.synchronize()
+        got[name] = (plan, outs)
+    rng = np.random.default_rng(19)
+    plan, outs = got["two-pass"]
+    assert [F.fht_plan_num_passes(plan.handle, v) for v in (0, 1)] == [2, 2]
+    for i in range(n):
+        _check_u8(plan, outs[i], imgs_np[i], 0, rng, 200)
+    assert torch.equal(outs, got["default"][1])
 
 
 def test_bench_ragged_512_graph_every_image():

@@ -63,3 +63,23 @@ def test_tuned_ragged_batch_is_exact_and_cached(F, tmp_path, monkeypatch):
     torch.cuda.synchronize()
     for a, b in zip(outs, outs2):
         assert torch.equal(a, b)
+
+
+def test_plain_schedule_pick_is_exact(F):
+    # both per-image schedules run every image of a small same-shape set; the
+    # pick is one of them, and the two-pass schedule really has two passes
+    from paper_2411_07351_amd import tuning as T
+    rng = WL.rng_for(3, salt=42)
+    imgs_np = WL.edge_maps(rng, 4, 300, 517)
+    imgs = [torch.from_numpy(i).cuda() for i in imgs_np]
+    name, times = T.tune_plain(imgs, "S", reps=2)
+    assert name in T.PLAIN_SCHEDULES and set(times) == set(T.PLAIN_SCHEDULES)
+    assert times[name] == min(times.values())
+    two = F.Plan(300, 517, "u8", "S", schedule=T.PLAIN_SCHEDULES["two-pass"])
+    assert [F.fht_plan_num_passes(two.handle, v) for v in (0, 1)] == [2, 2]
+    out = two.new_out()
+    two.forward(imgs[1], out)
+    torch.cuda.synchronize()
+    ref = native.hough4_u8(imgs_np[1], 0)
+    for q, g in enumerate(two.split_out(out)):
+        assert (g.cpu().numpy() == ref[q]).all(), q
