@@ -83,3 +83,20 @@ def test_plain_schedule_pick_is_exact(F):
     ref = native.hough4_u8(imgs_np[1], 0)
     for q, g in enumerate(two.split_out(out)):
         assert (g.cpu().numpy() == ref[q]).all(), q
+
+
+@pytest.mark.parametrize("split", [0, 1])
+def test_small_image_in_one_launch(F, split):
+    # 61 x 47 (the smallest workload): the two-pass schedule's 6-level first
+    # pass covers both order trees, so one launch does the whole transform
+    from paper_2411_07351_amd import tuning as T
+    img_np = WL.uniform_u8(WL.rng_for(1), 61, 47)
+    plan = F.Plan(61, 47, "u8", split, schedule=T.PLAIN_SCHEDULES["two-pass"])
+    assert F.fht_plan_num_launches(plan.handle) == 1
+    out = plan.new_out()
+    for _ in range(2):  # twice on one workspace: must repeat bit for bit
+        plan.forward(torch.from_numpy(img_np).cuda(), out)
+        torch.cuda.synchronize()
+        ref = native.hough4_u8(img_np, split)
+        for q, g in enumerate(plan.split_out(out)):
+            assert (g.cpu().numpy() == ref[q]).all(), q
