@@ -22,7 +22,8 @@ SCHEDULES = [None, None, None,
              dict(first_levels=4, max_levels=3, t_tile=8),
              dict(first_levels=6, max_levels=2, s_tile=256, lds_budget=98304),
              dict(first_levels=5, max_levels=4, t_tile=32, threads=256, threads_first=256),
-             dict(s_tile_first=64, s_tile=128, max_levels=5)]
+             dict(s_tile_first=64, s_tile=128, max_levels=5),
+             dict(first_levels=6, max_levels=4, lds_budget=163840)]  # the per-image two-pass
 SUBSETS = [(0, 1, 2, 3), (0, 1, 2, 3), (0, 1, 2, 3), (0,), (1, 3), (2, 3), (0, 2)]
 FULL_WORK = 3e9  # oracle work (R * C * (R + C)) up to which every output is compared
 
@@ -86,6 +87,21 @@ def test_fuzz_forward():
         torch.cuda.synchronize()
         got = [o.cpu().numpy() for o in plan.split_out(out)]
         _check(img, split, quadrants, got, rng)
+
+
+def test_fuzz_forward_two_pass_schedule():
+    # the schedule bench.py's per-image launches may pick, on random shapes
+    rng = np.random.default_rng(WL.SEED_BASE + 76)
+    for i in range(12):
+        kind = ["u8", "u8", "f32"][i % 3]
+        R, C = (int(v) for v in np.exp(rng.uniform(0.0, np.log(2600), size=2)))
+        split = int(rng.integers(0, 2))
+        img = _image(rng, kind, R, C)
+        plan = F.Plan(R, C, kind, split, schedule=SCHEDULES[-1])
+        out = plan.new_out()
+        plan.forward(torch.from_numpy(img).cuda(), out)
+        torch.cuda.synchronize()
+        _check(img, split, (0, 1, 2, 3), [o.cpu().numpy() for o in plan.split_out(out)], rng)
 
 
 @pytest.mark.parametrize("kind", ["u8", "f32"])
